@@ -1,0 +1,189 @@
+"""Pins of the oracle's filters against closed forms and exact references.
+
+* LL-PF (Section 2, Algorithm "Particle Filtering") against the Kalman
+  filter, which is exact for the linear-Gaussian local-level model.
+* LL-PL (Section 2, Algorithm "Particle Learning", Section 4 model) in the
+  known-parameter limit against the Kalman filter, and with unknown
+  variances against the exact 2-D quadrature of Kalman filters.
+* The sufficient-statistic recursions, checked along the tracked ancestry.
+* SV-PF against a point-mass grid filter; SV-PL in the known-parameter limit
+  against the same grid filter; the SV posterior against least squares; the
+  parameter draw against its posterior law.
+
+Monte Carlo comparisons average over seeds and use thresholds in standard
+errors estimated from the same seeds.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import closed_forms as cf
+from paper_1212_1639_amd import inputs
+
+LL = dict(x0_mean=0.0, x0_var=10.0)
+MU, PHI, SIG = -1.0, 0.95, 0.2
+SV0 = dict(x0_mean=MU, x0_var=SIG**2 / (1 - PHI**2))
+
+
+@pytest.fixture(scope="module")
+def y_ll():
+    return inputs.local_level(100, seed=0)[0]
+
+
+@pytest.fixture(scope="module")
+def y_sv():
+    return inputs.stochastic_volatility(100, seed=0)[0]
+
+
+def _runs(orc, model, n, seeds, y, scheme, **kw):
+    out = []
+    for s in seeds:
+        cfg = orc.make_config(model, n, s, scheme=scheme, **kw)
+        r = orc.run(cfg, y)
+        assert r["rc"] == 0
+        out.append(r)
+    return out
+
+
+def test_ll_pf_matches_kalman(orc, y_ll):
+    inc, m, _ = cf.kalman_ll(y_ll, 1.0, 0.1, 0.0, 10.0)
+    runs = _runs(orc, orc.LL_PF, 1024, range(32), y_ll, orc.MULTINOMIAL,
+                 sigma_v2=1.0, sigma_w2=0.1, **LL)
+    tot = np.array([r["loglik"].sum() for r in runs])
+    se = tot.std(ddof=1) / np.sqrt(tot.size)
+    # log of an unbiased estimate is biased down by about half its variance
+    assert abs(tot.mean() - inc.sum()) < 4 * se + 0.5 * tot.var()
+    means = np.array([r["moments"][:, 0] for r in runs])
+    z = (means.mean(0) - m) / (means.std(0, ddof=1) / np.sqrt(len(runs)))
+    assert np.sqrt(np.mean(z**2)) < 1.6 and np.abs(z).max() < 5.0
+    # per-step increments: each is the log of the step's average weight
+    incs = np.array([r["loglik"] for r in runs]).mean(0)
+    assert np.abs(incs - inc).max() < 0.1
+
+
+def test_ll_pl_known_parameter_limit_matches_kalman(orc, y_ll):
+    # IG(a, a*s) with a -> infinity pins the variances at s; PL is then the
+    # fully adapted filter of the Kalman model
+    inc, m, _ = cf.kalman_ll(y_ll, 1.0, 0.1, 0.0, 10.0)
+    runs = _runs(orc, orc.LL_PL, 1024, range(12), y_ll, orc.STRATIFIED,
+                 a_v=1e7, b_v=1e7, a_w=1e7, b_w=1e6, **LL)
+    tot = np.array([r["loglik"].sum() for r in runs])
+    se = tot.std(ddof=1) / np.sqrt(tot.size)
+    assert abs(tot.mean() - inc.sum()) < 4 * se + 0.5 * tot.var()
+    means = np.array([r["moments"][:, 0] for r in runs])
+    z = (means.mean(0) - m) / (means.std(0, ddof=1) / np.sqrt(len(runs)) + 1e-12)
+    assert np.sqrt(np.mean(z**2)) < 1.6
+    v = np.array([r["moments"][-1, 2:4] for r in runs]).mean(0)
+    assert v == pytest.approx([1.0, 0.1], rel=2e-3)
+
+
+def test_ll_pl_unknown_variances_matches_quadrature(orc, y_ll):
+    ex = cf.ll_pl_exact(y_ll, 2.0, 1.0, 2.0, 1.0, 0.0, 10.0, grid=200)
+    runs = _runs(orc, orc.LL_PL, 16384, range(4), y_ll, orc.STRATIFIED,
+                 a_v=2.0, b_v=1.0, a_w=2.0, b_w=1.0, **LL)
+    tot = np.array([r["loglik"].sum() for r in runs])
+    se = tot.std(ddof=1) / 2
+    assert abs(tot.mean() - ex["loglik"][-1]) < 4 * se + 0.02
+    last = np.array([r["moments"][-1] for r in runs])
+    for col, key in ((2, "e_v"), (4, "e_v"), (3, "e_w"), (5, "e_w"), (0, "e_x")):
+        se_c = last[:, col].std(ddof=1) / 2
+        assert abs(last[:, col].mean() - ex[key][-1]) < 4 * se_c + 2e-3, (col, key)
+
+
+def test_ll_pl_statistics_follow_the_ancestry(orc, y_ll):
+    # Step 3 of particle learning along the tracked ancestry:
+    #   b_v(t, j) - b_v(t-1, a_j) = (y_t - x_t)^2 / 2
+    #   b_w(t, j) - b_w(t-1, a_j) = (x_t - x_{t-1}(a_j))^2 / 2
+    cfg = orc.make_config(orc.LL_PL, 64, 3, scheme=orc.STRATIFIED, a_v=2.0, b_v=1.0,
+                          a_w=2.0, b_w=1.0, **LL)
+    r = orc.run(cfg, y_ll[:30], dump=True)
+    st, anc = r["state"], r["anc"]
+    for t in range(1, 30):
+        a = anc[t]
+        x, xp = st[t, 0], st[t - 1, 0, a]
+        assert np.allclose(st[t, 1] - st[t - 1, 1, a], 0.5 * (y_ll[t] - x) ** 2, atol=1e-12)
+        assert np.allclose(st[t, 2] - st[t - 1, 2, a], 0.5 * (x - xp) ** 2, atol=1e-12)
+    assert np.allclose(st[0, 1] - 1.0, 0.5 * (y_ll[0] - st[0, 0]) ** 2, atol=1e-12)
+
+
+def test_sv_pf_matches_grid_filter(orc, y_sv):
+    inc, em, _ = cf.sv_grid_filter(y_sv, MU, PHI, SIG**2, SV0["x0_mean"], SV0["x0_var"],
+                                   grid=1001)
+    runs = _runs(orc, orc.SV_PF, 4096, range(16), y_sv, orc.SYSTEMATIC,
+                 mu=MU, phi=PHI, sigma2=SIG**2, **SV0)
+    tot = np.array([r["loglik"].sum() for r in runs])
+    se = tot.std(ddof=1) / 4
+    assert abs(tot.mean() - inc.sum()) < 4 * se + 0.5 * tot.var()
+    means = np.array([r["moments"][:, 0] for r in runs])
+    z = (means.mean(0) - em) / (means.std(0, ddof=1) / 4)
+    assert np.sqrt(np.mean(z**2)) < 1.6 and np.abs(z).max() < 5.0
+
+
+def test_sv_pl_known_parameter_limit_matches_grid_filter(orc, y_sv):
+    inc, em, _ = cf.sv_grid_filter(y_sv, MU, PHI, SIG**2, SV0["x0_mean"], SV0["x0_var"],
+                                   grid=1001)
+    runs = _runs(orc, orc.SV_PL, 4096, range(8), y_sv, orc.SYSTEMATIC,
+                 prior_mean=[MU * (1 - PHI), PHI], prior_prec=[1e9, 0.0, 1e9],
+                 a_s=1e7, d_s=1e7 * SIG**2, **SV0)
+    tot = np.array([r["loglik"].sum() for r in runs])
+    se = tot.std(ddof=1) / np.sqrt(8)
+    assert abs(tot.mean() - inc.sum()) < 4 * se + 0.5 * tot.var()
+    th = np.array([r["moments"][-1, 2:5] for r in runs]).mean(0)
+    assert th == pytest.approx([MU * (1 - PHI), PHI, SIG**2], rel=1e-3)
+
+
+def test_sv_pl_sums_follow_the_ancestry(orc, y_sv):
+    cfg = orc.make_config(orc.SV_PL, 64, 5, scheme=orc.SYSTEMATIC,
+                          prior_mean=[MU * (1 - PHI), PHI], prior_prec=[1.0, 0.0, 1.0],
+                          a_s=2.0, d_s=0.04, **SV0)
+    r = orc.run(cfg, y_sv[:30], dump=True)
+    st, anc = r["state"], r["anc"]
+    for t in range(1, 30):
+        a = anc[t]
+        x, xp = st[t, 0], st[t - 1, 0, a]
+        inc = np.stack([np.ones_like(x), xp, xp * xp, x, xp * x, x * x])
+        assert np.allclose(st[t, 1:] - st[t - 1][1:][:, a], inc, atol=1e-10)
+    assert np.all(st[-1, 1] == 30)
+
+
+def test_sv_posterior_equals_least_squares(orc):
+    # the conjugate posterior equals least squares on the data augmented by
+    # the prior as pseudo-observations
+    rng = np.random.default_rng(1)
+    prior_mean = np.array([-0.05, 0.95])
+    P = np.array([[2.0, 0.3], [0.3, 1.5]])
+    cfg = orc.make_config(orc.SV_PL, 1, 0, prior_mean=prior_mean, prior_prec=[2.0, 0.3, 1.5],
+                          a_s=2.0, d_s=0.04)
+    for n in (0, 1, 5, 200):
+        xs = np.cumsum(rng.normal(size=n + 1)) * 0.3
+        xp, xn = xs[:-1], xs[1:]
+        sums = [n, xp.sum(), (xp * xp).sum(), xn.sum(), (xp * xn).sum(), (xn * xn).sum()]
+        post = orc.sv_posterior(cfg, sums)
+        R = np.linalg.cholesky(P).T  # P = R'R
+        A = np.vstack([R, np.column_stack([np.ones(n), xp])])
+        b = np.concatenate([R @ prior_mean, xn])
+        m, *_ = np.linalg.lstsq(A, b, rcond=None)
+        rss = ((A @ m - b) ** 2).sum()
+        assert post[3:5] == pytest.approx(m, rel=1e-9, abs=1e-12)
+        assert post[5] == 2.0 + n / 2
+        assert post[6] == pytest.approx(0.04 + 0.5 * rss, rel=1e-9)
+        assert post[0:3] == pytest.approx([2.0 + n, 0.3 + xp.sum(), 1.5 + (xp * xp).sum()])
+
+
+def test_sv_theta_draw_law(orc):
+    cfg = orc.make_config(orc.SV_PL, 1, 0, prior_mean=[0.0, 0.9], prior_prec=[1.0, 0.2, 3.0],
+                          a_s=3.0, d_s=0.5)
+    post = orc.sv_posterior(cfg, [10, 1.0, 4.0, 2.0, 1.5, 3.0])
+    rng = np.random.default_rng(2)
+    S = 8000
+    th = np.array([orc.sv_theta(post, *rng.standard_normal(1), rng.random(),
+                                *rng.standard_normal(2), seed=9, j=j, t=1) for j in range(S)])
+    assert stats.kstest(th[:, 2], stats.invgamma(post[5], scale=post[6]).cdf).pvalue > 1e-4
+    Lam = np.array([[post[0], post[1]], [post[1], post[2]]])
+    r = (th[:, :2] - post[3:5]) / np.sqrt(th[:, 2:3])
+    # (alpha, beta) | sigma^2 ~ N(m, sigma^2 Lambda^{-1}): whitened residuals are N(0, I)
+    Lc = np.linalg.cholesky(Lam)
+    wres = r @ Lc
+    for col in (0, 1):
+        assert stats.kstest(wres[:, col], "norm").pvalue > 1e-4
+    assert abs(np.corrcoef(wres.T)[0, 1]) < 0.05
