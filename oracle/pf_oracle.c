@@ -321,7 +321,8 @@ static double log_normal_pdf(double y, double mean, double var)
  * step ST_STEP(j,t) word 0 -> resampling uniform, words 1,2 -> normal.
  * Moments (weights w_t, before resampling): E x, Var x, ESS. */
 static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* loglik,
-                     double* mom, int64_t* anc_out, double* state_out, double* logw_out)
+                     double* mom, int64_t* anc_out, double* state_out, double* logw_out,
+                     const double* state0, int64_t t0, double y_prev)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -334,12 +335,22 @@ static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* log
     uint32_t w[4];
     double z[2];
     int rc = 0;
-    for (int64_t i = 0; i < N; ++i) {
+    for (int64_t i = 0; i < N && !state0; ++i) {
         words(c->seed, (uint32_t)i, 0, ST_INIT, 0, w);
         or_box_muller(unif(w[0], fp32), unif(w[1], fp32), z);
         x[i] = c->x0_mean + sqrt(c->x0_var) * z[0];
     }
-    for (int64_t t = 1; t <= T; ++t) {
+    if (state0) {
+        /* start from given particles x_{t0}; their weights are those of y_{t0} */
+        memcpy(x, state0, sizeof(double) * N);
+        if (t0 >= 1) {
+            for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y_prev, x[i], c->sigma_v2);
+            double M0, S0;
+            or_cdf(lw, N, q, &M0, &S0);
+        }
+    }
+    for (int64_t t = t0 + 1; t <= t0 + T; ++t) {
+        const int64_t r = t - t0 - 1; /* output row */
         if (t == 1) {
             for (int64_t j = 0; j < N; ++j) a[j] = j;
         } else {
@@ -352,24 +363,24 @@ static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* log
             xn[j] = x[a[j]] + sqrt(c->sigma_w2) * z[0];
         }
         memcpy(x, xn, sizeof(double) * N);
-        for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[t - 1], x[i], c->sigma_v2);
+        for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[r], x[i], c->sigma_v2);
         double M, S;
         or_cdf(lw, N, q, &M, &S);
         if (!(S > 0.0) || !isfinite(S) || !isfinite(M)) { rc = -1; }
-        loglik[t - 1] = M + log(S / (double)N);
+        loglik[r] = M + log(S / (double)N);
         double sw = 0, swx = 0, swxx = 0, sww = 0;
         for (int64_t i = 0; i < N; ++i) {
             double wi = exp(lw[i] - M);
             sw += wi; swx += wi * x[i]; swxx += wi * x[i] * x[i]; sww += wi * wi;
         }
-        double* m = mom + (t - 1) * OR_NMOM;
+        double* m = mom + r * OR_NMOM;
         for (int k = 0; k < OR_NMOM; ++k) m[k] = 0.0;
         m[0] = swx / sw;
         m[1] = swxx / sw - m[0] * m[0];
         m[2] = sw * sw / sww;
-        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[(t - 1) * N + j] = a[j];
-        if (state_out) memcpy(state_out + (t - 1) * N, x, sizeof(double) * N);
-        if (logw_out) memcpy(logw_out + (t - 1) * N, lw, sizeof(double) * N);
+        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[r * N + j] = a[j];
+        if (state_out) memcpy(state_out + r * N, x, sizeof(double) * N);
+        if (logw_out) memcpy(logw_out + r * N, lw, sizeof(double) * N);
     }
     free(x); free(xn); free(lw); free(q); free(u); free(a);
     return rc;
@@ -379,7 +390,8 @@ static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* log
  * (not in the paper): x_t = mu + phi (x_{t-1} - mu) + sigma Z,
  * y_t ~ N(0, exp(x_t)).  Same cycle, draws and moments as run_ll_pf. */
 static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* loglik,
-                     double* mom, int64_t* anc_out, double* state_out, double* logw_out)
+                     double* mom, int64_t* anc_out, double* state_out, double* logw_out,
+                     const double* state0, int64_t t0, double y_prev)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -393,12 +405,22 @@ static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* log
     double z[2];
     int rc = 0;
     const double sd = sqrt(c->sigma2);
-    for (int64_t i = 0; i < N; ++i) {
+    for (int64_t i = 0; i < N && !state0; ++i) {
         words(c->seed, (uint32_t)i, 0, ST_INIT, 0, w);
         or_box_muller(unif(w[0], fp32), unif(w[1], fp32), z);
         x[i] = c->x0_mean + sqrt(c->x0_var) * z[0];
     }
-    for (int64_t t = 1; t <= T; ++t) {
+    if (state0) {
+        /* start from given particles x_{t0}; their weights are those of y_{t0} */
+        memcpy(x, state0, sizeof(double) * N);
+        if (t0 >= 1) {
+            for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y_prev, 0.0, exp(x[i]));
+            double M0, S0;
+            or_cdf(lw, N, q, &M0, &S0);
+        }
+    }
+    for (int64_t t = t0 + 1; t <= t0 + T; ++t) {
+        const int64_t r = t - t0 - 1; /* output row */
         if (t == 1) {
             for (int64_t j = 0; j < N; ++j) a[j] = j;
         } else {
@@ -411,24 +433,24 @@ static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* log
             xn[j] = c->mu + c->phi * (x[a[j]] - c->mu) + sd * z[0];
         }
         memcpy(x, xn, sizeof(double) * N);
-        for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[t - 1], 0.0, exp(x[i]));
+        for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[r], 0.0, exp(x[i]));
         double M, S;
         or_cdf(lw, N, q, &M, &S);
         if (!(S > 0.0) || !isfinite(S) || !isfinite(M)) { rc = -1; }
-        loglik[t - 1] = M + log(S / (double)N);
+        loglik[r] = M + log(S / (double)N);
         double sw = 0, swx = 0, swxx = 0, sww = 0;
         for (int64_t i = 0; i < N; ++i) {
             double wi = exp(lw[i] - M);
             sw += wi; swx += wi * x[i]; swxx += wi * x[i] * x[i]; sww += wi * wi;
         }
-        double* m = mom + (t - 1) * OR_NMOM;
+        double* m = mom + r * OR_NMOM;
         for (int k = 0; k < OR_NMOM; ++k) m[k] = 0.0;
         m[0] = swx / sw;
         m[1] = swxx / sw - m[0] * m[0];
         m[2] = sw * sw / sww;
-        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[(t - 1) * N + j] = a[j];
-        if (state_out) memcpy(state_out + (t - 1) * N, x, sizeof(double) * N);
-        if (logw_out) memcpy(logw_out + (t - 1) * N, lw, sizeof(double) * N);
+        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[r * N + j] = a[j];
+        if (state_out) memcpy(state_out + r * N, x, sizeof(double) * N);
+        if (logw_out) memcpy(logw_out + r * N, lw, sizeof(double) * N);
     }
     free(x); free(xn); free(lw); free(q); free(u); free(a);
     return rc;
@@ -463,7 +485,8 @@ static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* log
  *   statistics from the theta sample), and the Rao-Blackwell means
  *   b/(a - 1) of the two IG posteriors. */
 static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* loglik,
-                     double* mom, int64_t* anc_out, double* state_out, double* logw_out)
+                     double* mom, int64_t* anc_out, double* state_out, double* logw_out,
+                     const double* state0, int64_t t0, double y_prev)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -477,7 +500,8 @@ static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* log
     uint32_t w[4];
     double g[2];
     int rc = 0;
-    for (int64_t i = 0; i < N; ++i) {
+    if (state0) memcpy(z, state0, sizeof(double) * N * F); /* z_{t0} given */
+    for (int64_t i = 0; i < N && !state0; ++i) {
         words(c->seed, (uint32_t)i, 0, ST_INIT, 0, w);
         or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
         double u_v = unif(w[2], fp32);
@@ -491,15 +515,16 @@ static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* log
         z[3 * N + i] = c->b_v / or_gamma_mt(c->a_v, z_v, u_v, c->seed, (uint32_t)i, 0, 0, fp32);
         z[4 * N + i] = c->b_w / or_gamma_mt(c->a_w, z_w, u_w, c->seed, (uint32_t)i, 0, 1, fp32);
     }
-    for (int64_t t = 1; t <= T; ++t) {
-        const double yt = y[t - 1];
+    for (int64_t t = t0 + 1; t <= t0 + T; ++t) {
+        const int64_t r = t - t0 - 1; /* output row */
+        const double yt = y[r];
         /* Step 1 */
         for (int64_t i = 0; i < N; ++i)
             lw[i] = log_normal_pdf(yt, z[0 * N + i], z[3 * N + i] + z[4 * N + i]);
         double M, S;
         or_cdf(lw, N, q, &M, &S);
         if (!(S > 0.0) || !isfinite(S) || !isfinite(M)) { rc = -1; }
-        loglik[t - 1] = M + log(S / (double)N);
+        loglik[r] = M + log(S / (double)N);
         or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
         or_resample(q, N, u, N, c->search, a);
         const double av = c->a_v + 0.5 * (double)t, aw = c->a_w + 0.5 * (double)t;
@@ -535,7 +560,7 @@ static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* log
             rv += z[1 * N + i] / (av - 1.0);
             rw += z[2 * N + i] / (aw - 1.0);
         }
-        double* mo = mom + (t - 1) * OR_NMOM;
+        double* mo = mom + r * OR_NMOM;
         for (int k = 0; k < OR_NMOM; ++k) mo[k] = 0.0;
         mo[0] = sx / N;
         mo[1] = sxx / N - mo[0] * mo[0];
@@ -543,9 +568,9 @@ static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* log
         mo[3] = sw / N;
         mo[4] = rv / N;
         mo[5] = rw / N;
-        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[(t - 1) * N + j] = a[j];
-        if (state_out) memcpy(state_out + (t - 1) * N * F, z, sizeof(double) * N * F);
-        if (logw_out) memcpy(logw_out + (t - 1) * N, lw, sizeof(double) * N);
+        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[r * N + j] = a[j];
+        if (state_out) memcpy(state_out + r * N * F, z, sizeof(double) * N * F);
+        if (logw_out) memcpy(logw_out + r * N, lw, sizeof(double) * N);
     }
     free(z); free(zn); free(lw); free(q); free(u); free(a);
     return rc;
@@ -640,7 +665,8 @@ void or_sv_theta(const double post[7], double z_g, double u_g, double z3, double
  *   E sigma^2 of the draws that produced x_t, ESS, and the Rao-Blackwell
  *   mean d/(a-1) of sigma^2 after the update. */
 static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* loglik,
-                     double* mom, int64_t* anc_out, double* state_out, double* logw_out)
+                     double* mom, int64_t* anc_out, double* state_out, double* logw_out,
+                     const double* state0, int64_t t0, double y_prev)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -656,13 +682,23 @@ static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* log
     uint32_t w[4];
     double g[2];
     int rc = 0;
-    for (int64_t i = 0; i < N; ++i) {
+    for (int64_t i = 0; i < N && !state0; ++i) {
         words(c->seed, (uint32_t)i, 0, ST_INIT, 0, w);
         or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
         z[0 * N + i] = c->x0_mean + sqrt(c->x0_var) * g[0];
         for (int f = 1; f < F; ++f) z[f * N + i] = 0.0;
     }
-    for (int64_t t = 1; t <= T; ++t) {
+    if (state0) {
+        /* start from given particles z_{t0}; their weights are those of y_{t0} */
+        memcpy(z, state0, sizeof(double) * N * F);
+        if (t0 >= 1) {
+            for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y_prev, 0.0, exp(z[i]));
+            double M0, S0;
+            or_cdf(lw, N, q, &M0, &S0);
+        }
+    }
+    for (int64_t t = t0 + 1; t <= t0 + T; ++t) {
+        const int64_t r = t - t0 - 1; /* output row */
         if (t == 1) {
             for (int64_t j = 0; j < N; ++j) a[j] = j;
         } else {
@@ -696,11 +732,11 @@ static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* log
             rb[j] = post[6] / (post[5] - 1.0);
         }
         memcpy(z, zn, sizeof(double) * N * F);
-        for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[t - 1], 0.0, exp(z[i]));
+        for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[r], 0.0, exp(z[i]));
         double M, S;
         or_cdf(lw, N, q, &M, &S);
         if (!(S > 0.0) || !isfinite(S) || !isfinite(M)) { rc = -1; }
-        loglik[t - 1] = M + log(S / (double)N);
+        loglik[r] = M + log(S / (double)N);
         double sw = 0, swx = 0, swxx = 0, sww = 0, sa = 0, sb = 0, ss = 0, sr = 0;
         for (int64_t i = 0; i < N; ++i) {
             double wi = exp(lw[i] - M), xi = z[i];
@@ -708,7 +744,7 @@ static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* log
             sa += wi * th[i]; sb += wi * th[N + i]; ss += wi * th[2 * N + i];
             sr += wi * rb[i];
         }
-        double* mo = mom + (t - 1) * OR_NMOM;
+        double* mo = mom + r * OR_NMOM;
         for (int k = 0; k < OR_NMOM; ++k) mo[k] = 0.0;
         mo[0] = swx / sw;
         mo[1] = swxx / sw - mo[0] * mo[0];
@@ -717,23 +753,37 @@ static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* log
         mo[4] = ss / sw;
         mo[5] = sw * sw / sww;
         mo[6] = sr / sw;
-        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[(t - 1) * N + j] = a[j];
-        if (state_out) memcpy(state_out + (t - 1) * N * F, z, sizeof(double) * N * F);
-        if (logw_out) memcpy(logw_out + (t - 1) * N, lw, sizeof(double) * N);
+        if (anc_out) for (int64_t j = 0; j < N; ++j) anc_out[r * N + j] = a[j];
+        if (state_out) memcpy(state_out + r * N * F, z, sizeof(double) * N * F);
+        if (logw_out) memcpy(logw_out + r * N, lw, sizeof(double) * N);
     }
     free(z); free(zn); free(th); free(rb); free(lw); free(q); free(u); free(a);
     return rc;
 }
 
+/* Run T steps from the prior (state0 = NULL, t0 = 0) or from given
+ * particles `state0` (the model's fields, [f * N + i]) that are the state
+ * after step t0; y[0..T-1] are then the observations of steps t0+1..t0+T and,
+ * for the models that weight after propagating, y_prev is the observation
+ * y_{t0} whose weights the first resampling uses.  Draws use the absolute
+ * time index, so a run from the state after t0 steps continues the same
+ * random streams. */
+int or_run_from(const or_config* c, const double* state0, int64_t t0, double y_prev,
+                const double* y, int64_t T, double* loglik, double* mom, int64_t* anc_out,
+                double* state_out, double* logw_out)
+{
+    if (!c || c->n < 1 || T < 0 || t0 < 0 || (t0 > 0 && !state0)) return -2;
+    switch (c->model) {
+    case OR_LL_PF: return run_ll_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
+    case OR_LL_PL: return run_ll_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
+    case OR_SV_PF: return run_sv_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
+    case OR_SV_PL: return run_sv_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
+    }
+    return -2;
+}
+
 int or_run(const or_config* c, const double* y, int64_t T, double* loglik, double* mom,
            int64_t* anc_out, double* state_out, double* logw_out)
 {
-    if (!c || c->n < 1 || T < 0) return -2;
-    switch (c->model) {
-    case OR_LL_PF: return run_ll_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out);
-    case OR_LL_PL: return run_ll_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out);
-    case OR_SV_PF: return run_sv_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out);
-    case OR_SV_PL: return run_sv_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out);
-    }
-    return -2;
+    return or_run_from(c, NULL, 0, 0.0, y, T, loglik, mom, anc_out, state_out, logw_out);
 }

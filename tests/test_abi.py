@@ -1,0 +1,79 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/pf.h declares, and validates configurations."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pf.h")
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_1212_1639_amd import pf as mod
+    if not os.path.exists(mod.LIB_PATH):
+        from paper_1212_1639_amd import build
+        build.build()
+    return mod
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(pf_[a-z_]+)\s*\(", text,
+                                 re.M)))
+
+
+def test_header_declarations_match_binding(pf):
+    assert declared_symbols() == sorted(pf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(pf):
+    out = subprocess.run(["nm", "-D", "--defined-only", pf.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (pf_[a-z_]+)$", out, re.M))
+    missing = [s for s in declared_symbols() if s not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(pf.LIB_PATH)
+    for s in declared_symbols():
+        assert hasattr(lib, s)
+
+
+def test_fields(pf):
+    assert [pf.lib().pf_fields(m) for m in range(4)] == [1, 5, 1, 6]
+    assert pf.lib().pf_fields(9) == 0
+
+
+def test_workspace_bytes_and_validation(pf):
+    good = pf.make_config("ll_pl", 1 << 20, 1, scheme=pf.STRATIFIED, a_v=2, b_v=1, a_w=2, b_w=1,
+                          x0_var=10)
+    nb = pf.workspace_bytes(good)
+    # records (2 x 5 fields x 4 B), CDF (2 x 4 B), ancestors (4 B) per particle
+    assert nb >= (1 << 20) * (40 + 8 + 4)
+    assert nb < (1 << 20) * 64
+    bad = [
+        dict(n=0), dict(n=1 << 31), dict(scheme=7), dict(precision=3), dict(strategy=9),
+        dict(items_per_thread=3), dict(x0_var=-1.0), dict(a_v=0.5),
+    ]
+    for b in bad:
+        kw = dict(model="ll_pl", n=1024, seed=1, scheme=pf.STRATIFIED, a_v=2, b_v=1, a_w=2, b_w=1,
+                  x0_var=10)
+        kw.update(b)
+        cfg = pf.make_config(kw.pop("model"), kw.pop("n"), kw.pop("seed"), **kw)
+        with pytest.raises(pf.PFError):
+            pf.workspace_bytes(cfg)
+    # the fused cut-point table lives in LDS: N above one window is refused
+    cfg = pf.make_config("ll_pf", 1 << 16, 1, strategy=pf.SEARCH_CUTPOINT, sigma_v2=1,
+                         sigma_w2=0.1, x0_var=10)
+    with pytest.raises(pf.PFError, match="cut-point"):
+        pf.workspace_bytes(cfg)
+    # merge needs sorted uniforms once the CDF exceeds a window
+    cfg = pf.make_config("ll_pf", 1 << 16, 1, scheme=pf.MULTINOMIAL, strategy=pf.SEARCH_MERGE,
+                         sigma_v2=1, sigma_w2=0.1, x0_var=10)
+    with pytest.raises(pf.PFError, match="sorted"):
+        pf.workspace_bytes(cfg)
+    cfg = pf.make_config("sv_pl", 100, 1, prior_prec=[1.0, 2.0, 1.0], a_s=2, d_s=0.04, x0_var=1)
+    with pytest.raises(pf.PFError, match="positive definite"):
+        pf.workspace_bytes(cfg)

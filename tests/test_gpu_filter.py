@@ -1,0 +1,168 @@
+"""GPU parity of the whole cycle (weights, CDF, resampling, propagation)
+through the C-ABI, against the CPU oracle on the same random streams.
+
+Double precision: ancestors bit-exact at every step and every particle's
+record within a relative 1e-9 (transcendental functions and summation
+order differ by ulps).  Single precision: the benchmark spec's tolerances
+|d loglik| <= 1e-3 T and filtered moments within 1e-4 relative (relative to
+max(|m|, posterior sd)) against the double-precision oracle driven by the
+same random words."""
+import numpy as np
+import pytest
+
+from tests import _cases as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1212_1639_amd import pf as mod
+    mod.lib()
+    return mod
+
+
+def _strategy(pf, name):
+    return {"auto": pf.SEARCH_AUTO, "binary": pf.SEARCH_BINARY, "cutpoint": pf.SEARCH_CUTPOINT,
+            "merge": pf.SEARCH_MERGE}[name]
+
+
+CASES = [
+    # model, n, scheme, strategy, items_per_thread, T
+    ("ll_pf", 1024, "multinomial", "auto", 0, 100),       # the 1024-particle FP64 workload
+    ("ll_pf", 1500, "multinomial", "cutpoint", 4, 20),
+    ("ll_pf", 3000, "stratified", "merge", 1, 20),
+    ("ll_pf", 3000, "multinomial", "binary", 1, 20),
+    ("ll_pf", 700, "systematic", "merge", 1, 20),
+    ("ll_pl", 3000, "stratified", "merge", 1, 20),
+    ("ll_pl", 1500, "multinomial", "auto", 4, 20),
+    ("ll_pl", 2049, "systematic", "binary", 2, 20),
+    ("sv_pf", 3000, "systematic", "merge", 1, 20),
+    ("sv_pf", 1000, "multinomial", "cutpoint", 4, 20),
+    ("sv_pl", 3000, "systematic", "merge", 1, 20),
+    ("sv_pl", 1777, "stratified", "binary", 2, 20),
+    ("sv_pl", 513, "multinomial", "auto", 1, 20),
+]
+
+
+@pytest.mark.parametrize("model,n,scheme,strat,ipt,T", CASES)
+def test_fp64_stepwise_parity(pf, orc, model, n, scheme, strat, ipt, T):
+    print(f"fp64 parity {model} n={n} {scheme} {strat} ipt={ipt} T={T}", flush=True)
+    y = C.data(model, T)
+    seed = 7
+    ocfg = C.oracle_config(orc, model, n, seed, scheme, fp32=False)
+    ref = orc.run(ocfg, y, dump=True)
+    assert ref["rc"] == 0
+    cfg = C.pf_config(pf, model, n, seed, scheme, fp32=False, strategy=_strategy(pf, strat),
+                      ipt=ipt)
+    f = pf.Filter(cfg)
+    lag = 1 if model == "ll_pl" else 0
+    for t in range(1, T + 1):
+        f.step(y[t - 1])
+        rec, anc, tt = f.particles()
+        assert tt == t - lag
+        ll = f.loglik()
+        assert abs(ll - ref["loglik"][:t].sum()) < 1e-9 * max(1.0, abs(ll)), (t, ll)
+        if tt == 0:
+            continue
+        want_anc = ref["anc"][tt - 1]
+        bad = np.nonzero(anc != want_anc)[0]
+        assert bad.size == 0, (t, bad[:5], anc[bad[:5]], want_anc[bad[:5]])
+        want = C.oracle_to_record(orc, model, ocfg, ref["state"][tt - 1])
+        np.testing.assert_allclose(rec, want, rtol=1e-9, atol=1e-11)
+    mom = f.moments()
+    k = mom.size
+    np.testing.assert_allclose(mom, ref["moments"][-1, :k], rtol=1e-8, atol=1e-10)
+    f.close()
+
+
+def _rel_err(a, b, sd):
+    return np.abs(a - b) / np.maximum(np.abs(b), sd)
+
+
+@pytest.mark.parametrize("model,n,scheme,T", [
+    ("ll_pl", 1 << 16, "stratified", 100),
+    ("ll_pf", 1 << 16, "stratified", 100),
+    ("sv_pl", 1 << 16, "systematic", 100),
+    ("sv_pf", 1 << 16, "systematic", 100),
+])
+def test_fp32_tolerances(pf, orc, model, n, scheme, T):
+    print(f"fp32 tolerance {model} n={n} {scheme} T={T}", flush=True)
+    y = C.data(model, T)
+    ocfg = C.oracle_config(orc, model, n, 3, scheme, fp32=True)
+    ref = orc.run(ocfg, y)
+    cfg = C.pf_config(pf, model, n, 3, scheme, fp32=True)
+    f = pf.Filter(cfg)
+    f.step(y)
+    ll = f.loglik()
+    mom = f.moments()
+    f.close()
+    assert abs(ll - ref["loglik"].sum()) <= 1e-3 * T, (ll, ref["loglik"].sum())
+    want = ref["moments"][-1, : mom.size]
+    sd = np.sqrt(max(want[1], 1e-300))
+    err = _rel_err(mom[0], want[0], sd)
+    print("loglik", ll, ref["loglik"].sum(), "moments", mom, want, "rel err E x", err)
+    assert err <= 1e-4
+    # parameter means (scale: themselves)
+    others = [i for i in range(2, mom.size) if not (model.endswith("pf") or
+                                                     (model == "sv_pl" and i == 5))]
+    for i in others:
+        assert abs(mom[i] - want[i]) <= 1e-4 * abs(want[i]), (i, mom[i], want[i])
+
+
+def test_ll_pl_call_pattern_does_not_change_results(pf):
+    # the cycle weights y_{t+1} before it propagates with y_t; stepping one
+    # observation at a time, in blocks, or with moments read in between must
+    # give the same filter
+    y = C.data("ll_pl", 40)
+    outs = []
+    for pattern in ("all", "single", "moments_between"):
+        cfg = C.pf_config(pf, "ll_pl", 5000, 11, "stratified", fp32=False)
+        f = pf.Filter(cfg)
+        if pattern == "all":
+            f.step(y)
+        else:
+            for t in range(40):
+                f.step(y[t])
+                if pattern == "moments_between" and t % 7 == 3:
+                    f.moments()
+        ll = f.loglik()
+        mom = f.moments()
+        rec, anc, tt = f.particles()
+        f.close()
+        outs.append((ll, mom, rec, tt))
+    for ll, mom, rec, tt in outs[1:]:
+        assert tt == outs[0][3] == 40
+        assert abs(ll - outs[0][0]) < 1e-10
+        np.testing.assert_allclose(mom, outs[0][1], rtol=1e-10)
+        np.testing.assert_array_equal(rec, outs[0][2])
+
+
+def test_repeat_runs_are_identical(pf):
+    y = C.data("sv_pl", 30)
+    res = []
+    for _ in range(2):
+        cfg = C.pf_config(pf, "sv_pl", 100000, 5, "systematic", fp32=True)
+        f = pf.Filter(cfg)
+        f.step(y)
+        res.append((f.loglik(), f.particles()[0]))
+        f.close()
+    assert abs(res[0][0] - res[1][0]) < 1e-9
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+
+
+def test_errors(pf):
+    cfg = C.pf_config(pf, "ll_pf", 1000, 1, "multinomial", fp32=False)
+    f = pf.Filter(cfg)
+    with pytest.raises(pf.PFError, match="not finite"):
+        f.step([1.0, float("nan")])
+    f.step([0.5])
+    # an observation so far away that every weight underflows to zero
+    f.step([1e200])
+    with pytest.raises(pf.PFError) as e:
+        f.loglik()
+    assert e.value.code == pf.EDEGENERATE
+    f.close()

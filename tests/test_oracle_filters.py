@@ -187,3 +187,18 @@ def test_sv_theta_draw_law(orc):
     for col in (0, 1):
         assert stats.kstest(wres[:, col], "norm").pvalue > 1e-4
     assert abs(np.corrcoef(wres.T)[0, 1]) < 0.05
+
+
+@pytest.mark.parametrize("model", ["ll_pf", "ll_pl", "sv_pf", "sv_pl"])
+def test_run_from_a_state_continues_the_same_streams(orc, model):
+    # a run from the particles after t0 steps reproduces the rest of a full run
+    from tests import _cases as C
+    y = C.data(model, 12)
+    cfg = C.oracle_config(orc, model, 300, 4, "stratified", fp32=False)
+    full = orc.run(cfg, y, dump=True)
+    t0 = 5
+    part = orc.run(cfg, y[t0:], dump=True, state0=full["state"][t0 - 1], t0=t0,
+                   y_prev=y[t0 - 1])
+    np.testing.assert_array_equal(part["anc"], full["anc"][t0:])
+    np.testing.assert_array_equal(part["state"], full["state"][t0:])
+    np.testing.assert_array_equal(part["loglik"], full["loglik"][t0:])
