@@ -1,0 +1,172 @@
+"""Benchmark of the fused particle-filter cycle on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one full cycle of the filter (weights, CDF scan, resampling,
+propagation with the particle-learning statistics) over all particles of
+one filter, launched through the C-ABI.  Prints ONE JSON line: whole-job
+particle-steps/s, the roofline of the cycle kernel (algorithmic bytes per
+launch over its average duration, from HIP events on the filter's stream),
+and the CPU oracle timed on a bounded sample of the same workload.
+
+Workloads (all synthetic; data simulated from the model):
+  ll_pl_2p20  particle learning, local-level model, unknown variances under
+              IG(2, 1) priors, N = 2^20, T = 500, stratified, FP32 (default)
+  sv_pl_2p26  particle learning, stochastic volatility, unknown
+              (alpha, beta, sigma^2), N = 2^26, T = 1000, systematic, FP32
+  ll_pf_1024  bootstrap filter, local-level model, known variances,
+              N = 1024, T = 100, multinomial, FP64
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "ll_pl_2p20": dict(model="ll_pl", n=1 << 20, T=500, scheme="stratified", fp32=True,
+                       params=dict(x0_mean=0.0, x0_var=10.0, a_v=2.0, b_v=1.0, a_w=2.0, b_w=1.0),
+                       # record x, b_v, b_w, sigma_v2, sigma_w2 (4 B each), read + written;
+                       # in-tile CDF prefix written then read (4 B each)
+                       bytes_per_particle=2 * 20 + 8),
+    "sv_pl_2p26": dict(model="sv_pl", n=1 << 26, T=1000, scheme="systematic", fp32=True,
+                       params=dict(x0_mean=-1.0, x0_var=0.04 / (1 - 0.95**2),
+                                   prior_mean=[-0.05, 0.95], prior_prec=[1.0, 0.0, 1.0],
+                                   a_s=2.0, d_s=0.04),
+                       # record x + 5 per-particle statistics (4 B each) read + written,
+                       # CDF prefix written then read
+                       bytes_per_particle=2 * 24 + 8),
+    "ll_pf_1024": dict(model="ll_pf", n=1024, T=100, scheme="multinomial", fp32=False,
+                       params=dict(x0_mean=0.0, x0_var=10.0, sigma_v2=1.0, sigma_w2=0.1),
+                       bytes_per_particle=2 * 8 + 16),
+}
+
+
+def data(w, T):
+    from paper_1212_1639_amd import inputs
+    if w["model"].startswith("ll"):
+        return inputs.local_level(T, seed=0)[0]
+    return inputs.stochastic_volatility(T, seed=0)[0]
+
+
+def cpu_baseline(w, y, budget_s=15.0):
+    """The oracle as it stands, sequential (1 thread), on the first few steps
+    of the same workload: enough steps for about `budget_s` seconds."""
+    import oracle
+    model = {"ll_pf": oracle.LL_PF, "ll_pl": oracle.LL_PL, "sv_pf": oracle.SV_PF,
+             "sv_pl": oracle.SV_PL}[w["model"]]
+    scheme = {"multinomial": oracle.MULTINOMIAL, "stratified": oracle.STRATIFIED,
+              "systematic": oracle.SYSTEMATIC}[w["scheme"]]
+    n = w["n"]
+    # a short probe sizes the sample
+    cfg = oracle.make_config(model, n, 1, scheme=scheme, fp32_words=w["fp32"], **w["params"])
+    t0 = time.perf_counter()
+    oracle.run(cfg, y[:1])
+    per_step = max(time.perf_counter() - t0, 1e-6)
+    steps = int(max(1, min(len(y), budget_s / per_step)))
+    t0 = time.perf_counter()
+    oracle.run(cfg, y[:steps])
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} of {w['T']} steps at N={n} (sequential FP64 C oracle, "
+                      f"initialisation included)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the workload's T)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ll_pl_2p20", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--items-per-thread", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs one filter per GPU and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1212_1639_amd import pf
+
+    w = WORKLOADS[args.workload]
+    K = args.steps or w["T"]
+    W = args.warmup
+    y = data(w, max(K, W, 1))
+    scheme = {"multinomial": pf.MULTINOMIAL, "stratified": pf.STRATIFIED,
+              "systematic": pf.SYSTEMATIC}[w["scheme"]]
+    cfg = pf.make_config(w["model"], w["n"], 1, scheme=scheme,
+                         precision=pf.FP32 if w["fp32"] else pf.FP64,
+                         items_per_thread=args.items_per_thread, **w["params"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    if W > 0:
+        warm = pf.Filter(cfg, stream=stream)
+        warm.step(y[:W])
+        warm.loglik()
+        warm.close()
+        del warm
+
+    f = pf.Filter(cfg, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    f.step(y[:K])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    loglik = f.loglik()
+    mom = f.moments()
+    f.close()
+
+    n = w["n"]
+    value = n * K / wall
+    # one cycle launch per step: its average duration from the events on the
+    # filter's stream (includes the launch gaps between consecutive cycles)
+    kern_s = ev_ms * 1e-3 / K
+    bytes_launch = w["bytes_per_particle"] * n
+    achieved = bytes_launch / kern_s / 1e9
+    out = {
+        "metric": "particle-steps/sec @1 MI355X (batched vs plain), %HBM peak; p50/p99 step latency",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w["fp32"] else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "model": w["model"], "n_particles": n,
+                   "T": w["T"], "scheme": w["scheme"], "form": "plain"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step", "kernel_avg_us": kern_s * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "loglik": loglik,
+        "moments": [float(v) for v in mom],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, y)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * pf.h - C-ABI of libpf_mi355x.so: the fully parallel particle-filter /
+ * particle-learning cycle of McAlinn & Nakatsuma, "Parallel Resampling for
+ * Fully Parallelized Particle Filters" (arXiv:1212.1639), on one AMD MI355X
+ * (gfx950).
+ *
+ * The problem statement the calls follow is the paper's (Section 2): a state
+ * space model y_t ~ p(y_t | x_t, theta), x_t ~ p(x_t | x_{t-1}, theta)
+ * (equation (ssm)), a prior for the initial particles, N particles, and
+ * observations that arrive one at a time; the outputs are the filtered
+ * approximation of the state, posterior statistics of theta (Section 2,
+ * after Algorithm "Particle Learning") and the log-likelihood implied by the
+ * weight normaliser (equation (pf.resampling)).  As the paper requires
+ * (end of Section 3.2), every particle stays in device memory between steps:
+ * data cross to the host only when the caller asks for the log-likelihood
+ * or the moments.
+ *
+ * Conventions for every call:
+ *   - Return value 0 (PF_OK) or a negative PF_E* code; the text of the last
+ *     error of the calling thread is available from pf_last_error().  No C++
+ *     exception crosses this interface.
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or a torch CUDA
+ *     tensor's data_ptr); everything else is host memory.
+ *   - A handle is bound to one HIP stream and is not thread-safe; calls on
+ *     one handle must not overlap.  pf_step never synchronises the stream.
+ *   - Particle and ancestor indices are 0-based.
+ */
+#ifndef PF_MI355X_H
+#define PF_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define PF_OK 0
+#define PF_EINVAL (-1)      /* bad argument (message says which)              */
+#define PF_ENOMEM (-2)      /* workspace too small or device allocation failed */
+#define PF_EDEVICE (-3)     /* a HIP runtime call failed                       */
+#define PF_EDEGENERATE (-4) /* every weight of some step was zero or not finite:
+                               the normaliser of equation (pf.resampling) is
+                               undefined.  Sticky: reported by pf_loglik and
+                               pf_moments from then on                         */
+
+/* ---------------------------------------------------------------- models */
+/* Local-level ("stochastic trend with noise") model of Section 4, equation
+ * (trend+noise): y_t = x_t + v_t, v_t ~ N(0, sigma_v2); x_t = x_{t-1} + w_t,
+ * w_t ~ N(0, sigma_w2); x_0 ~ N(x0_mean, x0_var).
+ *   PF_LL_PF: known variances, bootstrap filter (Section 2, Algorithm
+ *             "Particle Filtering").
+ *   PF_LL_PL: unknown variances with priors sigma_v2 ~ IG(a_v, b_v),
+ *             sigma_w2 ~ IG(a_w, b_w) (shape, scale), particle learning
+ *             (Section 2, Algorithm "Particle Learning", the experiment of
+ *             Section 4).
+ * Stochastic volatility (not in the paper): x_t = mu + phi (x_{t-1} - mu) +
+ * sigma eta_t, y_t ~ N(0, exp(x_t)); x_0 ~ N(x0_mean, x0_var).
+ *   PF_SV_PF: known (mu, phi, sigma2), bootstrap filter.
+ *   PF_SV_PL: unknown (alpha, beta, sigma^2) = (mu (1 - phi), phi, sigma^2)
+ *             with the conjugate prior (alpha, beta) | sigma^2 ~
+ *             N(prior_mean, sigma^2 Lambda0^{-1}), sigma^2 ~ IG(a_s, d_s),
+ *             learned in the propagate-weight-resample order. */
+enum pf_model { PF_LL_PF = 0, PF_LL_PL = 1, PF_SV_PF = 2, PF_SV_PL = 3 };
+
+/* Resampling uniforms (Section 3.1): multinomial i.i.d.; stratified, one per
+ * stratum [j/N, (j+1)/N]; systematic, one offset shared by all strata. */
+enum pf_scheme { PF_MULTINOMIAL = 0, PF_STRATIFIED = 1, PF_SYSTEMATIC = 2 };
+
+/* Arithmetic of states and weights.  The CDF tile sums, normaliser and
+ * log-likelihood are always accumulated in double precision. */
+enum pf_precision { PF_FP32 = 0, PF_FP64 = 1 };
+
+/* How the inverse CDF a_j = min{k : q(k) >= u_j} is found (Section 3.2).
+ * Every strategy returns the same ancestors for the same CDF and uniforms.
+ *   PF_SEARCH_AUTO:     library choice (cut-point when the CDF fits one
+ *                       work-group's LDS window, merge for sorted uniforms,
+ *                       bisection otherwise).
+ *   PF_SEARCH_BINARY:   bisection per uniform.
+ *   PF_SEARCH_CUTPOINT: the paper's parallel cut-point method: table
+ *                       I_k = min{i : q(i) > (k-1)/N} built by the
+ *                       parallelized cut-point search, then a climb from
+ *                       I_{ceil(N u)}; the climb is bounded, falling back
+ *                       to bisection above the start point.
+ *   PF_SEARCH_MERGE:    work-group cooperative merge of sorted uniforms
+ *                       against the CDF staged in LDS. */
+enum pf_strategy {
+    PF_SEARCH_AUTO = 0,
+    PF_SEARCH_BINARY = 1,
+    PF_SEARCH_CUTPOINT = 2,
+    PF_SEARCH_MERGE = 3
+};
+
+/* PF_FLAG_KEEP_ANCESTORS: also store each step's ancestor indices (4 bytes
+ * per particle per step) so pf_debug_particles can return them; off by
+ * default because the cycle itself never reads them back. */
+#define PF_FLAG_KEEP_ANCESTORS 1
+/* PF_FLAG_LOOKBACK_SCAN: form the CDF's tile prefixes in the cycle kernel
+ * itself by a decoupled look-back over the tiles' (max, sum) aggregates,
+ * instead of the default: tiles store their (max, sum) and one extra
+ * work-group scans them in a fixed order.  Both give the same CDF up to
+ * rounding; the default is deterministic and faster on MI355X. */
+#define PF_FLAG_LOOKBACK_SCAN 2
+
+typedef struct pf_config {
+    int32_t model;            /* enum pf_model                                 */
+    int32_t scheme;           /* enum pf_scheme                                */
+    int32_t precision;        /* enum pf_precision                             */
+    int32_t strategy;         /* enum pf_strategy                              */
+    int64_t n_particles;      /* N >= 1 and N <= 2^31 - 1                       */
+    uint64_t seed;            /* key of the counter-based generator             */
+    int32_t items_per_thread; /* 0 = library choice, else one of 1, 2, 4, 8     */
+    int32_t flags;            /* bitwise OR of PF_FLAG_*; other bits must be 0  */
+    double x0_mean, x0_var;   /* prior of x_0                                  */
+    double sigma_v2, sigma_w2;/* PF_LL_PF: known variances                     */
+    double a_v, b_v, a_w, b_w;/* PF_LL_PL: inverse-gamma priors                */
+    double mu, phi, sigma2;   /* PF_SV_PF: known parameters                    */
+    double prior_mean[2];     /* PF_SV_PL: mean of (alpha, beta) given sigma^2  */
+    double prior_prec[3];     /* PF_SV_PL: Lambda0 = [[p0, p1], [p1, p2]], SPD  */
+    double a_s, d_s;          /* PF_SV_PL: inverse-gamma prior of sigma^2       */
+} pf_config;
+
+typedef struct pf_filter pf_filter;
+
+/* Number of values each particle keeps in device memory for `model`
+ * (the record layout of pf_debug_particles); 0 for an unknown model. */
+int pf_fields(int32_t model);
+
+/* Device bytes a filter with this configuration needs: particle records
+ * (double-buffered, structure of arrays), the CDF, per-tile scan state and
+ * a few scalars.  0 if the configuration is invalid (see pf_last_error). */
+size_t pf_workspace_bytes(const pf_config* cfg);
+
+/* Create a filter and sample its initial particles (Step 0 of both
+ * algorithms of Section 2) on `hip_stream` (NULL = the null stream).
+ *   workspace_dev: caller-owned device memory of at least
+ *       pf_workspace_bytes(cfg) bytes, 256-byte aligned, that outlives the
+ *       handle; NULL makes the library allocate (and later free) it.
+ *   out: receives the handle.
+ * Errors: PF_EINVAL (bad configuration, misaligned workspace), PF_ENOMEM
+ * (ws_bytes too small, allocation failed), PF_EDEVICE. */
+int pf_create(const pf_config* cfg, void* workspace_dev, size_t ws_bytes, void* hip_stream,
+              pf_filter** out);
+
+/* Assimilate n_obs >= 1 observations y[0..n_obs-1] (host memory, read
+ * before the call returns) in order: for each one, a full cycle of weights,
+ * CDF, resampling and propagation runs on the device (Section 3.2: the whole
+ * cycle is parallel).  Asynchronous with respect to the host.  Errors:
+ * PF_EINVAL (n_obs < 1, a non-finite observation: nothing is launched),
+ * PF_EDEVICE. */
+int pf_step(pf_filter* f, const double* y, int64_t n_obs);
+
+/* Synchronise the filter's stream and return in *out the log-likelihood
+ * estimate sum_t log( (1/N) sum_i p(y_t | particle i) ) over the
+ * observations assimilated so far (0 before any).  Errors: PF_EDEGENERATE,
+ * PF_EDEVICE. */
+int pf_loglik(pf_filter* f, double* out);
+
+/* Synchronise and return posterior statistics of the latest time step in
+ * out[0..n-1], n = the model's count (PF_LL_PF, PF_SV_PF: 3; PF_LL_PL: 6;
+ * PF_SV_PL: 7); n_out must be >= n, extra entries are set to 0.
+ *   PF_LL_PF, PF_SV_PF (weights of the latest step, before resampling):
+ *     [E x_t, Var x_t, effective sample size].
+ *   PF_LL_PL (equal weights, after propagation):
+ *     [E x_t, Var x_t, mean of drawn sigma_v2, mean of drawn sigma_w2,
+ *      Rao-Blackwell mean b_v/(a_v - 1), Rao-Blackwell mean b_w/(a_w - 1)].
+ *   PF_SV_PL (weights of the latest step):
+ *     [E x_t, Var x_t, E alpha, E beta, E sigma^2 of the draws,
+ *      effective sample size, Rao-Blackwell mean of sigma^2].
+ * For PF_LL_PL this may launch the propagation of the latest observation
+ * (the cycle weights y_{t+1} before it propagates with y_t). */
+int pf_moments(pf_filter* f, double* out, int32_t n_out);
+
+/* Release a handle and, if the library allocated it, its workspace.
+ * NULL is accepted.  Synchronises the stream first. */
+int pf_destroy(pf_filter* f);
+
+/* Text of the calling thread's last error ("" if none). */
+const char* pf_last_error(void);
+
+/* ------------------------------------------------------- test surfaces  */
+/* Inverse-CDF search alone (Section 3.2), the exact-parity surface of the
+ * resampling step: anc_dev[j] = min{k : cdf_dev[k] >= u_dev[j]}, or n-1 when
+ * no entry reaches u_dev[j].
+ *   cdf_dev: n >= 1 non-decreasing doubles (checked on the device:
+ *            PF_EINVAL if decreasing anywhere or not finite);
+ *   u_dev:   m >= 0 doubles in (0, 1];  anc_dev: m int32 outputs;
+ *   strategy: PF_SEARCH_BINARY, PF_SEARCH_CUTPOINT or PF_SEARCH_MERGE
+ *            (AUTO = MERGE).  Synchronises the stream before returning.
+ * n must be <= 2^31 - 1.  Errors: PF_EINVAL, PF_ENOMEM, PF_EDEVICE. */
+int pf_debug_search(const double* cdf_dev, const double* u_dev, int64_t n, int64_t m,
+                    int32_t strategy, int32_t* anc_dev, void* hip_stream);
+
+/* Copy the current particles to host memory for small-N tests: the record
+ * as pf_fields(model) arrays of N values (float for PF_FP32, double for
+ * PF_FP64), followed by N int32 ancestors that produced them (identity when
+ * no resampling happened; all -1 unless the filter was created with
+ * PF_FLAG_KEEP_ANCESTORS).  bytes must be >= that size.  *t_out (if not
+ * NULL) receives the number of propagations done so far.  Synchronises.
+ * Record fields: PF_LL_PF, PF_SV_PF: x.  PF_LL_PL: x, b_v, b_w, sigma_v2,
+ * sigma_w2.  PF_SV_PL: x, L01, L11, eta0, eta1, d, where Lambda = [[L00,
+ * L01], [L01, L11]] and eta are the precision and the precision-weighted
+ * mean of the (alpha, beta) posterior and d its inverse-gamma scale
+ * (L00 = p0 + t and the shape a_s + t/2 are the same for every particle). */
+int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_MI355X_H */

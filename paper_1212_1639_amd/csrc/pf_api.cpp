@@ -1,0 +1,475 @@
+// Host runtime of libpf_mi355x.so: configuration checks, workspace layout,
+// the per-filter launch sequence and the C-ABI of include/pf.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "pf.h"
+#include "pf_internal.h"
+
+namespace pf {
+hipError_t launch_step(int model, bool fp64, int ipt, const StepArgs& a, int grid, hipStream_t s,
+                       bool init);
+hipError_t launch_scan_tiles(const double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
+                             int32_t* hint, Totals* tot, DevState* st, hipStream_t s);
+hipError_t launch_moments(int model, const double* partials, int32_t num_tiles, int64_t n,
+                          int32_t weighted, uint32_t t, const ModelParams& p, DevState* st,
+                          hipStream_t s);
+hipError_t launch_search(int strategy, const double* q, int64_t n, const double* u, int64_t m,
+                         int32_t* anc, int32_t* table, int32_t* bad, hipStream_t s);
+}  // namespace pf
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const std::string& msg) {
+    g_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(PF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kBlock = 256;
+constexpr size_t kAlign = 256;
+constexpr int64_t kCutMax = 2048;  // largest CDF with an in-LDS cut-point table
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int model_fields(int32_t model) {
+    switch (model) {
+    case PF_LL_PF: return 1;
+    case PF_LL_PL: return 5;
+    case PF_SV_PF: return 1;
+    case PF_SV_PL: return 6;
+    }
+    return 0;
+}
+
+int model_moments(int32_t model) {
+    switch (model) {
+    case PF_LL_PF: return 3;
+    case PF_LL_PL: return 6;
+    case PF_SV_PF: return 3;
+    case PF_SV_PL: return 7;
+    }
+    return 0;
+}
+
+int choose_ipt(const pf_config& c) {
+    if (c.items_per_thread) return c.items_per_thread;
+    // measured on MI355X: 4 items per thread up to 2^22 particles, 8 above
+    if (c.n_particles <= (int64_t(1) << 22)) return 4;
+    return 8;
+}
+
+struct Layout {
+    int ipt = 0, ts = 0, num_tiles = 0, fields = 0, rsz = 0, strategy = 0;
+    int64_t pitch = 0;
+    size_t rec[2], c[2], samp[2], tiles[2], tot[2], status, state, partials, anc, agg, ab, hint,
+        total;
+    bool lookback = false;
+};
+
+bool finite_all(std::initializer_list<double> v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+// Validates `c` and fills the workspace layout; returns 0 or PF_EINVAL.
+int plan(const pf_config* c, Layout* L) {
+    if (!c) return fail(PF_EINVAL, "pf_config is NULL");
+    if (c->model < PF_LL_PF || c->model > PF_SV_PL) return fail(PF_EINVAL, "unknown model");
+    if (c->scheme < PF_MULTINOMIAL || c->scheme > PF_SYSTEMATIC)
+        return fail(PF_EINVAL, "unknown resampling scheme");
+    if (c->precision != PF_FP32 && c->precision != PF_FP64)
+        return fail(PF_EINVAL, "precision must be PF_FP32 or PF_FP64");
+    if (c->strategy < PF_SEARCH_AUTO || c->strategy > PF_SEARCH_MERGE)
+        return fail(PF_EINVAL, "unknown search strategy");
+    if (c->n_particles < 1 || c->n_particles > INT32_MAX)
+        return fail(PF_EINVAL, "n_particles must be in [1, 2^31 - 1]");
+    if (c->flags & ~(PF_FLAG_KEEP_ANCESTORS | PF_FLAG_LOOKBACK_SCAN))
+        return fail(PF_EINVAL, "unknown bits in flags");
+    const int ipt = choose_ipt(*c);
+    if (ipt != 1 && ipt != 2 && ipt != 4 && ipt != 8)
+        return fail(PF_EINVAL, "items_per_thread must be 0, 1, 2, 4 or 8");
+    if (!finite_all({c->x0_mean, c->x0_var}) || !(c->x0_var > 0))
+        return fail(PF_EINVAL, "x0_var must be finite and > 0");
+    switch (c->model) {
+    case PF_LL_PF:
+        if (!(c->sigma_v2 > 0) || !(c->sigma_w2 > 0) || !finite_all({c->sigma_v2, c->sigma_w2}))
+            return fail(PF_EINVAL, "sigma_v2 and sigma_w2 must be finite and > 0");
+        break;
+    case PF_LL_PL:
+        if (!(c->a_v >= 1) || !(c->a_w >= 1) || !(c->b_v > 0) || !(c->b_w > 0) ||
+            !finite_all({c->a_v, c->a_w, c->b_v, c->b_w}))
+            return fail(PF_EINVAL, "IG priors need shape >= 1 and scale > 0");
+        break;
+    case PF_SV_PF:
+        if (!(c->sigma2 > 0) || !finite_all({c->mu, c->phi, c->sigma2}))
+            return fail(PF_EINVAL, "sigma2 must be finite and > 0");
+        break;
+    case PF_SV_PL: {
+        const double p0 = c->prior_prec[0], p1 = c->prior_prec[1], p2 = c->prior_prec[2];
+        if (!(p0 > 0) || !(p0 * p2 - p1 * p1 > 0) || !finite_all({p0, p1, p2}))
+            return fail(PF_EINVAL, "prior_prec must be symmetric positive definite");
+        if (!(c->a_s >= 1) || !(c->d_s > 0) || !finite_all({c->a_s, c->d_s, c->prior_mean[0],
+                                                            c->prior_mean[1]}))
+            return fail(PF_EINVAL, "IG prior of sigma^2 needs shape >= 1 and scale > 0");
+        break;
+    }
+    }
+    L->ipt = ipt;
+    L->ts = kBlock * ipt;
+    const int64_t n = c->n_particles;
+    L->num_tiles = static_cast<int>((n + L->ts - 1) / L->ts);
+    L->fields = model_fields(c->model);
+    L->rsz = c->precision == PF_FP64 ? 8 : 4;
+    L->pitch = static_cast<int64_t>(align_up(static_cast<size_t>(n), 64));
+    const int64_t win = 2 * static_cast<int64_t>(L->ts);
+    const int64_t cut_max = win < kCutMax ? win : kCutMax;
+    int strat = c->strategy;
+    if (strat == PF_SEARCH_AUTO) {
+        if (c->scheme == PF_MULTINOMIAL)
+            strat = n <= cut_max ? PF_SEARCH_CUTPOINT : (n <= win ? PF_SEARCH_MERGE : PF_SEARCH_BINARY);
+        else
+            strat = PF_SEARCH_MERGE;
+    }
+    if (strat == PF_SEARCH_CUTPOINT && n > cut_max)
+        return fail(PF_EINVAL, "the fused cut-point search builds its table in LDS and needs "
+                               "N <= min(2048, 2 * 256 * items_per_thread); use "
+                               "PF_SEARCH_BINARY or PF_SEARCH_MERGE (or pf_debug_search)");
+    if (strat == PF_SEARCH_MERGE && c->scheme == PF_MULTINOMIAL && n > win)
+        return fail(PF_EINVAL, "the merge search needs sorted uniforms (stratified or systematic) "
+                               "when N exceeds one LDS window");
+    L->strategy = strat;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, kAlign);
+        return at;
+    };
+    const size_t rec_bytes = static_cast<size_t>(L->fields) * L->pitch * L->rsz;
+    for (int b = 0; b < 2; ++b) L->rec[b] = take(rec_bytes);
+    for (int b = 0; b < 2; ++b) L->c[b] = take(static_cast<size_t>(L->pitch) * L->rsz);
+    for (int b = 0; b < 2; ++b)
+        L->samp[b] = take(static_cast<size_t>(L->num_tiles) * pf::kSegments * L->rsz);
+    for (int b = 0; b < 2; ++b) L->tiles[b] = take(sizeof(pf::TileInfo) * L->num_tiles);
+    for (int b = 0; b < 2; ++b) L->tot[b] = take(sizeof(pf::Totals));
+    L->status = take(sizeof(uint64_t) * pf::kStatusWords * L->num_tiles);
+    L->state = take(sizeof(pf::DevState));
+    L->partials = take(sizeof(double) * pf::kPartialStride * L->num_tiles);
+    L->anc = (c->flags & PF_FLAG_KEEP_ANCESTORS) ? take(sizeof(int32_t) * L->pitch) : 0;
+    L->agg = take(sizeof(double) * 2 * L->num_tiles);
+    L->ab = take(sizeof(pf::TileAB) * L->num_tiles);
+    L->hint = take(sizeof(int32_t) * (L->num_tiles + 1));
+    L->lookback = (c->flags & PF_FLAG_LOOKBACK_SCAN) != 0;
+    L->total = off;
+    return PF_OK;
+}
+
+pf::ModelParams params_of(const pf_config& c) {
+    pf::ModelParams p{};
+    p.x0_mean = c.x0_mean;
+    p.x0_var = c.x0_var;
+    p.sigma_v2 = c.sigma_v2;
+    p.sigma_w2 = c.sigma_w2;
+    p.a_v = c.a_v;
+    p.b_v = c.b_v;
+    p.a_w = c.a_w;
+    p.b_w = c.b_w;
+    p.mu = c.mu;
+    p.phi = c.phi;
+    p.sigma2 = c.sigma2;
+    p.b0a = c.prior_mean[0];
+    p.b0b = c.prior_mean[1];
+    p.p0 = c.prior_prec[0];
+    p.p1 = c.prior_prec[1];
+    p.p2 = c.prior_prec[2];
+    p.a_s = c.a_s;
+    p.d_s = c.d_s;
+    return p;
+}
+
+}  // namespace
+
+struct pf_filter {
+    pf_config cfg;
+    Layout L;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    bool owns_ws = false;
+    int cur = 0;             // record buffer holding the current particles
+    int cdf = 0;             // buffer holding the latest CDF
+    bool have_cdf = false;   // the latest particles carry weights (a CDF)
+    bool pending = false;    // particle learning: weighted for y_pend, not yet propagated
+    double y_pend = 0.0;
+    uint32_t t = 0;          // propagations done
+    uint32_t epoch = 0;      // look-back tag of the latest weighting launch
+    int32_t weighted_partials = 0;
+    pf::ModelParams mp;
+
+    template <typename T>
+    T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+
+    pf::StepArgs args() {
+        pf::StepArgs a{};
+        a.n = cfg.n_particles;
+        a.pitch = L.pitch;
+        a.num_tiles = L.num_tiles;
+        a.scheme = cfg.scheme;
+        a.strategy = L.strategy;
+        a.seed = cfg.seed;
+        a.status = at<uint64_t>(L.status);
+        a.st = at<pf::DevState>(L.state);
+        a.partials = at<double>(L.partials);
+        a.anc_out = (cfg.flags & PF_FLAG_KEEP_ANCESTORS) ? at<int32_t>(L.anc) : nullptr;
+        a.scan = L.lookback ? pf::kScanLookback : pf::kScanTiles;
+        a.ab_in = at<pf::TileAB>(L.ab);
+        a.hint_in = at<int32_t>(L.hint);
+        a.agg_out = at<double>(L.agg);
+        a.p = mp;
+        return a;
+    }
+
+    // One cycle launch.  resample: draw ancestors from the latest CDF;
+    // propagate: move with y_prop; weight: score against y_weight.
+    int launch(bool resample, bool propagate, bool weight, double y_prop, double y_weight) {
+        pf::StepArgs a = args();
+        a.flags = (resample ? pf::kResample : 0) | (propagate ? pf::kPropagate : 0) |
+                  (weight ? pf::kWeight : 0);
+        const bool weighted_mom = weight && cfg.model != PF_LL_PL;
+        if (weighted_mom) a.flags |= pf::kWeightedMoments;
+        a.t = t + 1;
+        a.y_prop = y_prop;
+        a.y_weight = y_weight;
+        a.rec_in = ws + L.rec[cur];
+        a.rec_out = ws + L.rec[1 - cur];
+        a.c_in = ws + L.c[cdf];
+        a.samp_in = ws + L.samp[cdf];
+        a.samp_out = ws + L.samp[1 - cdf];
+        a.tiles_in = at<pf::TileInfo>(L.tiles[cdf]);
+        a.tot_in = at<pf::Totals>(L.tot[cdf]);
+        a.c_out = ws + L.c[1 - cdf];
+        a.tiles_out = at<pf::TileInfo>(L.tiles[1 - cdf]);
+        a.tot_out = at<pf::Totals>(L.tot[1 - cdf]);
+        if (weight) {
+            if (++epoch == 0) epoch = 1;
+        }
+        a.epoch = epoch;
+        hipError_t e = pf::launch_step(cfg.model, cfg.precision == PF_FP64, L.ipt, a, L.num_tiles,
+                                       stream, false);
+        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        if (weight && !L.lookback) {
+            e = pf::launch_scan_tiles(a.agg_out, L.num_tiles, cfg.n_particles, L.ts,
+                                      at<pf::TileAB>(L.ab), at<int32_t>(L.hint), a.tot_out, a.st,
+                                      stream);
+            if (e != hipSuccess) return hip_fail(e, "tile scan launch");
+        }
+        if (propagate) {
+            cur = 1 - cur;
+            ++t;
+        }
+        if (weight) {
+            cdf = 1 - cdf;
+            have_cdf = true;
+        } else if (propagate) {
+            have_cdf = false;
+        }
+        weighted_partials = weighted_mom ? 1 : 0;
+        return PF_OK;
+    }
+};
+
+extern "C" {
+
+int pf_fields(int32_t model) { return model_fields(model); }
+
+size_t pf_workspace_bytes(const pf_config* cfg) {
+    Layout L;
+    if (plan(cfg, &L) != PF_OK) return 0;
+    return L.total;
+}
+
+int pf_create(const pf_config* cfg, void* workspace, size_t ws_bytes, void* hip_stream,
+              pf_filter** out) {
+    if (!out) return fail(PF_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    int rc = plan(cfg, &L);
+    if (rc != PF_OK) return rc;
+    pf_filter* f = new (std::nothrow) pf_filter();
+    if (!f) return fail(PF_ENOMEM, "host allocation failed");
+    f->cfg = *cfg;
+    f->L = L;
+    f->stream = static_cast<hipStream_t>(hip_stream);
+    f->mp = params_of(*cfg);
+    if (workspace) {
+        if (ws_bytes < L.total) {
+            delete f;
+            return fail(PF_ENOMEM, "workspace smaller than pf_workspace_bytes()");
+        }
+        if (reinterpret_cast<uintptr_t>(workspace) % kAlign) {
+            delete f;
+            return fail(PF_EINVAL, "workspace must be 256-byte aligned");
+        }
+        f->ws = static_cast<char*>(workspace);
+    } else {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, L.total);
+        if (e != hipSuccess) {
+            delete f;
+            return fail(PF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        f->ws = static_cast<char*>(p);
+        f->owns_ws = true;
+    }
+    // Step 0 of both algorithms: sample the initial particles
+    pf::StepArgs a = f->args();
+    a.rec_out = f->ws + L.rec[0];
+    hipError_t e = pf::launch_step(cfg->model, cfg->precision == PF_FP64, L.ipt, a, L.num_tiles,
+                                   f->stream, true);
+    if (e != hipSuccess) {
+        if (f->owns_ws) hipFree(f->ws);
+        delete f;
+        return hip_fail(e, "init kernel launch");
+    }
+    *out = f;
+    g_error.clear();
+    return PF_OK;
+}
+
+int pf_step(pf_filter* f, const double* y, int64_t n_obs) {
+    if (!f) return fail(PF_EINVAL, "filter is NULL");
+    if (!y || n_obs < 1) return fail(PF_EINVAL, "need n_obs >= 1 observations");
+    for (int64_t i = 0; i < n_obs; ++i)
+        if (!std::isfinite(y[i])) return fail(PF_EINVAL, "observation is not finite");
+    for (int64_t i = 0; i < n_obs; ++i) {
+        int rc;
+        if (f->cfg.model == PF_LL_PL) {
+            // Step 1 weights the current particles with p(y_{t+1} | z_t), so a
+            // cycle propagates with y_t only once y_{t+1} is known
+            if (!f->pending) {
+                rc = f->launch(false, false, true, 0.0, y[i]);
+            } else {
+                rc = f->launch(true, true, true, f->y_pend, y[i]);
+            }
+            f->pending = true;
+            f->y_pend = y[i];
+        } else {
+            rc = f->launch(f->have_cdf, true, true, y[i], y[i]);
+        }
+        if (rc != PF_OK) return rc;
+    }
+    return PF_OK;
+}
+
+int pf_loglik(pf_filter* f, double* out) {
+    if (!f || !out) return fail(PF_EINVAL, "NULL argument");
+    pf::DevState st;
+    hipError_t e = hipMemcpyAsync(&st, f->at<pf::DevState>(f->L.state), sizeof(st),
+                                  hipMemcpyDeviceToHost, f->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_loglik copy");
+    *out = st.loglik;
+    if (st.flags & pf::kDegenerate) return fail(PF_EDEGENERATE, "a step's weights were all zero or not finite");
+    return PF_OK;
+}
+
+int pf_moments(pf_filter* f, double* out, int32_t n_out) {
+    if (!f || !out) return fail(PF_EINVAL, "NULL argument");
+    const int need = model_moments(f->cfg.model);
+    if (n_out < need) return fail(PF_EINVAL, "n_out smaller than the model's moment count");
+    if (f->cfg.model == PF_LL_PL && f->pending) {
+        int rc = f->launch(true, true, false, f->y_pend, 0.0);
+        if (rc != PF_OK) return rc;
+        f->pending = false;
+    }
+    hipError_t e = pf::launch_moments(f->cfg.model, f->at<double>(f->L.partials), f->L.num_tiles,
+                                      f->cfg.n_particles, f->weighted_partials, f->t, f->mp,
+                                      f->at<pf::DevState>(f->L.state), f->stream);
+    if (e != hipSuccess) return hip_fail(e, "moment kernel launch");
+    pf::DevState st;
+    e = hipMemcpyAsync(&st, f->at<pf::DevState>(f->L.state), sizeof(st), hipMemcpyDeviceToHost,
+                       f->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_moments copy");
+    for (int k = 0; k < n_out; ++k) out[k] = k < need ? st.moments[k] : 0.0;
+    if (st.flags & pf::kDegenerate) return fail(PF_EDEGENERATE, "a step's weights were all zero or not finite");
+    return PF_OK;
+}
+
+int pf_destroy(pf_filter* f) {
+    if (!f) return PF_OK;
+    hipError_t e = hipStreamSynchronize(f->stream);
+    if (f->owns_ws) hipFree(f->ws);
+    delete f;
+    if (e != hipSuccess) return hip_fail(e, "pf_destroy synchronise");
+    return PF_OK;
+}
+
+const char* pf_last_error(void) { return g_error.c_str(); }
+
+int pf_debug_search(const double* cdf_dev, const double* u_dev, int64_t n, int64_t m,
+                    int32_t strategy, int32_t* anc_dev, void* hip_stream) {
+    if (!cdf_dev || n < 1 || n > INT32_MAX) return fail(PF_EINVAL, "need a CDF of 1 <= n < 2^31 entries");
+    if (m < 0 || (m > 0 && (!u_dev || !anc_dev))) return fail(PF_EINVAL, "bad uniforms / output");
+    if (strategy == PF_SEARCH_AUTO) strategy = PF_SEARCH_MERGE;
+    if (strategy < PF_SEARCH_BINARY || strategy > PF_SEARCH_MERGE)
+        return fail(PF_EINVAL, "unknown search strategy");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int32_t* table = nullptr;
+    int32_t* bad = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&bad), sizeof(int32_t));
+    if (e != hipSuccess) return fail(PF_ENOMEM, "hipMalloc of the check flag failed");
+    if (strategy == PF_SEARCH_CUTPOINT) {
+        e = hipMalloc(reinterpret_cast<void**>(&table), sizeof(int32_t) * static_cast<size_t>(n));
+        if (e != hipSuccess) {
+            hipFree(bad);
+            return fail(PF_ENOMEM, "hipMalloc of the cut-point table failed");
+        }
+    }
+    int rc = PF_OK;
+    e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) e = pf::launch_search(strategy, cdf_dev, n, u_dev, m, anc_dev, table, bad, s);
+    int32_t hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "pf_debug_search");
+    else if (hbad) rc = fail(PF_EINVAL, "CDF is decreasing somewhere or not finite");
+    hipFree(bad);
+    if (table) hipFree(table);
+    return rc;
+}
+
+int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_out) {
+    if (!f || !host_out) return fail(PF_EINVAL, "NULL argument");
+    const int64_t n = f->cfg.n_particles;
+    const size_t rec = static_cast<size_t>(f->L.fields) * n * f->L.rsz;
+    if (bytes < rec + sizeof(int32_t) * n) return fail(PF_EINVAL, "host buffer too small");
+    char* dst = static_cast<char*>(host_out);
+    hipError_t e = hipSuccess;
+    for (int fld = 0; fld < f->L.fields && e == hipSuccess; ++fld)
+        e = hipMemcpyAsync(dst + static_cast<size_t>(fld) * n * f->L.rsz,
+                           f->ws + f->L.rec[f->cur] + static_cast<size_t>(fld) * f->L.pitch * f->L.rsz,
+                           static_cast<size_t>(n) * f->L.rsz, hipMemcpyDeviceToHost, f->stream);
+    if (e == hipSuccess) {
+        if (f->cfg.flags & PF_FLAG_KEEP_ANCESTORS)
+            e = hipMemcpyAsync(dst + rec, f->ws + f->L.anc, sizeof(int32_t) * n,
+                               hipMemcpyDeviceToHost, f->stream);
+        else
+            std::memset(dst + rec, 0xff, sizeof(int32_t) * n);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_debug_particles");
+    if (t_out) *t_out = f->t;
+    return PF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1128 @@
+// HIP kernels of the particle-filter cycle for gfx950 (wave64).
+//
+// One launch of k_step advances a filter by one cycle (Section 3.2: the whole
+// cycle runs in parallel on the device):
+//   1. each output slot j forms its resampling uniform u_j (Section 3.1) and
+//      finds its ancestor a_j = min{k : q(k) >= u_j} in the previous step's
+//      CDF (Section 3.2), either cooperatively for a tile of sorted uniforms
+//      (merge against the CDF staged in LDS), by the paper's cut-point table
+//      built in LDS, or by bisection;
+//   2. gathers the ancestor's record from the structure-of-arrays buffer,
+//      propagates it (and, for particle learning, updates its statistics and
+//      draws its parameters) and writes the new record;
+//   3. scores the new particle (log-weight), takes the tile's max-shifted
+//      sum of exp(l - m) and its in-tile inclusive prefix (the CDF, equation
+//      (resample.cdf), up to the tile's offset and the global normaliser).
+// The tile prefixes over all tiles then come from one of two scans:
+//   - tile scan (default): every tile stores its (max, sum); k_scan_tiles, a
+//     single work-group, scans them in a fixed order, normalises them into
+//     per-tile affine constants (q = a + c[k] b), forms the log-likelihood
+//     increment and, for sorted uniforms, the source tile of every output
+//     tile's first uniform (search hints);
+//   - decoupled look-back: each tile obtains its exclusive prefix inside
+//     k_step from the (max, sum) aggregates of its predecessors, and the
+//     tile with the last ticket forms the totals.
+// The normalised CDF is never materialised.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pf_internal.h"
+#include "pf_models.hpp"
+
+namespace pf {
+
+constexpr int kWave = 64;
+// Largest CDF whose cut-point table is built in LDS by the cycle kernel.
+constexpr int kCutMax = 2048;
+// Predecessor tiles each lane inspects per look-back round.
+constexpr int kLookPer = 4;
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Inclusive prefix sum over the wave (Kogge-Stone).
+__device__ __forceinline__ double wave_incl_sum(double v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double o = __shfl_up(v, off, kWave);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_incl_max(double v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double o = __shfl_up(v, off, kWave);
+        if (lane >= off) v = fmax(v, o);
+    }
+    return v;
+}
+
+// (max, sum of exp(l - max)) monoid of the max-shifted log-sum-exp.
+struct Agg {
+    double m, s;
+};
+__device__ __forceinline__ Agg agg_identity() { return {-INFINITY, 0.0}; }
+__device__ __forceinline__ Agg agg_combine(Agg a, Agg b) {
+    if (a.m == -INFINITY) return b;
+    if (b.m == -INFINITY) return a;
+    const double m = fmax(a.m, b.m);
+    return {m, a.s * exp(a.m - m) + b.s * exp(b.m - m)};
+}
+__device__ __forceinline__ Agg wave_agg(Agg v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        Agg o{__shfl_xor(v.m, off, kWave), __shfl_xor(v.s, off, kWave)};
+        v = agg_combine(v, o);
+    }
+    return v;
+}
+
+// ------------------------------------------------------------ look-back words
+// Each 64-bit word = (epoch << 32) | 32 payload bits; relaxed agent-scope
+// atomics keep every word single-copy atomic and coherent across the XCDs'
+// L2s without a release/acquire fence (which would write back the L2).
+__device__ __forceinline__ void put_word(uint64_t* p, uint32_t epoch, uint32_t bits) {
+    __hip_atomic_store(p, (static_cast<uint64_t>(epoch) << 32) | bits, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t get_word(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put_agg(uint64_t* p, uint32_t epoch, Agg a) {
+    const uint64_t mb = __double_as_longlong(a.m), sb = __double_as_longlong(a.s);
+    put_word(p + 0, epoch, static_cast<uint32_t>(mb));
+    put_word(p + 1, epoch, static_cast<uint32_t>(mb >> 32));
+    put_word(p + 2, epoch, static_cast<uint32_t>(sb));
+    put_word(p + 3, epoch, static_cast<uint32_t>(sb >> 32));
+}
+// Returns true (and the value) when all four words carry `epoch`.
+__device__ __forceinline__ bool get_agg(const uint64_t* p, uint32_t epoch, Agg& a) {
+    const uint64_t w0 = get_word(p + 0), w1 = get_word(p + 1);
+    const uint64_t w2 = get_word(p + 2), w3 = get_word(p + 3);
+    const uint64_t tag = static_cast<uint64_t>(epoch);
+    if ((w0 >> 32) != tag || (w1 >> 32) != tag || (w2 >> 32) != tag || (w3 >> 32) != tag)
+        return false;
+    a.m = __longlong_as_double(static_cast<long long>((w0 & 0xffffffffull) | (w1 << 32)));
+    a.s = __longlong_as_double(static_cast<long long>((w2 & 0xffffffffull) | (w3 << 32)));
+    return true;
+}
+
+// ------------------------------------------------------------ CDF of the previous step
+// q(k) = A_b + c[k] B_b for k in tile b.  A_b, B_b come either from the
+// tile-scan table (ab != nullptr) or from the look-back's (max, sum) form.
+template <typename R>
+struct PrevCdf {
+    const R* c;
+    const TileInfo* tiles;
+    const TileAB* ab;
+    double M, S;
+    int64_t n;
+    int32_t ts;  // elements per tile
+
+    __device__ __forceinline__ void tile_ab(int64_t b, double& ta, double& tb) const {
+        if (ab) {
+            const TileAB v = ab[b];
+            ta = v.a;
+            tb = v.b;
+        } else {
+            const TileInfo ti = tiles[b];
+            ta = ti.s_ex == 0.0 ? 0.0 : ti.s_ex * exp(ti.m_ex - M) / S;
+            tb = exp(ti.m_b - M) / S;
+        }
+    }
+    // q(k); the last entry is 1 by definition (equation resample.cdf).
+    __device__ __forceinline__ double at(int64_t k) const {
+        if (k >= n - 1) return 1.0;
+        double ta, tb;
+        tile_ab(k / ts, ta, tb);
+        return fma(static_cast<double>(c[k]), tb, ta);
+    }
+};
+
+struct PlainCdf {
+    const double* q;
+    int64_t n;
+    __device__ __forceinline__ double at(int64_t k) const { return q[k]; }
+};
+
+// First k in [lo, hi] with q(k) >= u, or hi if none, found by one wave with
+// 64 strided probes per round.
+template <typename CDF>
+__device__ int64_t wave_search(const CDF& cdf, double u, int64_t lo, int64_t hi) {
+    const int lane = lane_id();
+    while (hi > lo) {
+        const int64_t len = hi - lo + 1;
+        const int64_t stride = (len + kWave - 1) / kWave;
+        int64_t k = lo + static_cast<int64_t>(lane) * stride;
+        if (k > hi) k = hi;
+        const bool ge = cdf.at(k) >= u;
+        const uint64_t mask = __ballot(ge);
+        if (stride == 1) {
+            return mask ? lo + static_cast<int64_t>(__ffsll(static_cast<long long>(mask)) - 1) : hi;
+        }
+        if (mask == 0) {
+            const int64_t last = lo + static_cast<int64_t>(kWave - 1) * stride;
+            if (last >= hi) return hi;
+            lo = last + 1;
+        } else {
+            const int first = __ffsll(static_cast<long long>(mask)) - 1;
+            const int64_t kf = lo + static_cast<int64_t>(first) * stride;
+            hi = kf > hi ? hi : kf;
+            if (first > 0) lo = lo + static_cast<int64_t>(first - 1) * stride + 1;
+        }
+    }
+    return lo;
+}
+
+// Bisection by one thread: first k in [lo, hi] with q(k) >= u, else hi.
+template <typename CDF>
+__device__ int64_t thread_search(const CDF& cdf, double u, int64_t lo, int64_t hi) {
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (cdf.at(mid) >= u) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// First index in s_q[0, cnt) with value >= u, or cnt.
+__device__ __forceinline__ int lds_lower_bound(const double* s_q, int cnt, double u) {
+    int lo = 0, hi = cnt;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_q[mid] >= u) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Stage q(w0 .. w0+cnt-1) in LDS and make it non-decreasing (running max
+// from `floor`): rounding of the tile-wise representation can make adjacent
+// values differ by an ulp in the wrong direction, and every in-LDS search
+// below assumes a monotone array.  Loads are coalesced; the running max is a
+// per-thread pass over a contiguous chunk plus a block scan of the chunk
+// maxima.  Ends with a barrier.
+template <int BLOCK, typename R>
+__device__ void stage_window(const PrevCdf<R>& P, int64_t w0, int cnt, double floor, double* s_q,
+                             double* s_ta, double* s_tb, double* s_red) {
+    const int tid = threadIdx.x;
+    const int64_t b0 = w0 / P.ts, b1 = (w0 + cnt - 1) / P.ts;
+    const int nb = static_cast<int>(b1 - b0 + 1);
+    for (int k = tid; k < nb; k += BLOCK) P.tile_ab(b0 + k, s_ta[k], s_tb[k]);
+    __syncthreads();
+    for (int k = tid; k < cnt; k += BLOCK) {
+        const int64_t g = w0 + k;
+        double v = 1.0;
+        if (g < P.n - 1) {
+            const int bb = static_cast<int>(g / P.ts - b0);
+            v = fma(static_cast<double>(P.c[g]), s_tb[bb], s_ta[bb]);
+        }
+        s_q[k] = v;
+    }
+    __syncthreads();
+    const int per = (cnt + BLOCK - 1) / BLOCK;
+    const int k0 = tid * per;
+    const int k1 = min(cnt, k0 + per);
+    double run = -INFINITY;
+    for (int k = k0; k < k1; ++k) run = fmax(run, s_q[k]);
+    const int lane = lane_id(), wave = tid / kWave;
+    const double incl = wave_incl_max(run);
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    double carry = floor;
+    for (int w = 0; w < wave; ++w) carry = fmax(carry, s_red[w]);
+    double excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = -INFINITY;
+    carry = fmax(carry, excl);
+    for (int k = k0; k < k1; ++k) {
+        carry = fmax(carry, s_q[k]);
+        s_q[k] = carry;
+    }
+    __syncthreads();
+}
+
+// Cut-point table of Section 3.2 built in LDS over s_q[0, n) (the whole
+// CDF): with L_j = ceil(n q(j)), element j owns entries L_{j-1}+1 .. L_j
+// (1-based) and writes its index there; the last element also owns every
+// entry above L_n.  Ends with a barrier.
+template <int BLOCK>
+__device__ void build_cutpoints(const double* s_q, int n, int* s_cut) {
+    const double dn = static_cast<double>(n);
+    for (int j = threadIdx.x; j < n; j += BLOCK) {
+        double cj = ceil(dn * s_q[j]);
+        const int Lj = cj < 0.0 ? 0 : (cj > dn ? n : static_cast<int>(cj));
+        int Lp = 0;
+        if (j > 0) {
+            const double cp = ceil(dn * s_q[j - 1]);
+            Lp = cp < 0.0 ? 0 : (cp > dn ? n : static_cast<int>(cp));
+        }
+        const int top = (j == n - 1) ? n : Lj;
+        for (int k = top; k > Lp; --k) s_cut[k - 1] = j;
+    }
+    __syncthreads();
+}
+
+// Cut-point draw (Section 3.2, Algorithm "Parallelized Cut-Point Method"):
+// start at I_{ceil(n u)} and climb while u is above the CDF; after 16 climbs
+// finish by bisection above the current point (same answer, bounded work).
+__device__ __forceinline__ int cutpoint_draw(const double* s_q, const int* s_cut, int n, double u) {
+    double ce = ceil(static_cast<double>(n) * u);
+    int e = ce < 1.0 ? 1 : (ce > static_cast<double>(n) ? n : static_cast<int>(ce));
+    int k = s_cut[e - 1];
+    for (int c = 0; c < 16 && k < n - 1 && u > s_q[k]; ++c) ++k;
+    if (k < n - 1 && u > s_q[k]) {
+        const int r = lds_lower_bound(s_q + k + 1, n - 1 - k, u);
+        k = k + 1 + r;
+        if (k > n - 1) k = n - 1;
+    }
+    return k;
+}
+
+__device__ __forceinline__ double resample_uniform(int32_t scheme, int64_t j, int64_t n,
+                                                   uint32_t w0, double u_sys) {
+    if (scheme == kMultinomial) return unit64(w0);
+    if (scheme == kStratified)
+        return (static_cast<double>(j) + unit64(w0)) / static_cast<double>(n);
+    return (static_cast<double>(j) + u_sys) / static_cast<double>(n);
+}
+
+// ------------------------------------------------------------ shared memory
+template <int BLOCK, int IPT>
+struct StepSmem {
+    static constexpr int TS = BLOCK * IPT;
+    static constexpr int WIN = 2 * TS;
+    static constexpr int NW = BLOCK / kWave;
+    double q[WIN];           // staged CDF window; reused for the scan
+    int cut[kCutMax];        // cut-point table (CDFs of up to kCutMax entries)
+    double ta[8], tb[8];     // per-tile affine constants of the window
+    double red[NW * 16];     // reductions
+    int64_t lo, hi;
+    uint32_t tile;
+    int32_t pad;
+    double ex_m, ex_s;
+};
+
+// ------------------------------------------------------------ the cycle kernel
+template <int MODEL, typename R, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
+    using MD = ModelDef<MODEL>;
+    constexpr int F = MD::F, NG = MD::NG;
+    constexpr int TS = BLOCK * IPT, NW = BLOCK / kWave;
+    constexpr int WIN = StepSmem<BLOCK, IPT>::WIN;
+    __shared__ StepSmem<BLOCK, IPT> sm;
+
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const bool weight = (A.flags & kWeight) != 0;
+    const bool resample = (A.flags & kResample) != 0;
+    const bool propagate = (A.flags & kPropagate) != 0;
+    const bool weighted_mom = (A.flags & kWeightedMoments) != 0;
+    const int64_t n = A.n;
+
+    // Tile order: with the look-back, a dynamic ticket, so that every tile a
+    // look-back waits on was handed out earlier and is resident or done.
+    const bool lookback = weight && A.scan == kScanLookback;
+    uint32_t tile;
+    if (lookback) {
+        if (tid == 0)
+            sm.tile = __hip_atomic_fetch_add(&A.st->ticket, 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        tile = sm.tile;
+    } else {
+        tile = blockIdx.x;
+    }
+    const int64_t j0 = static_cast<int64_t>(tile) * TS;
+
+    // ---------------------------------------------------------- 1. ancestors
+    Words w[IPT];
+    int32_t anc[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+        anc[i] = static_cast<int32_t>(j < n ? j : n - 1);
+        if (propagate && j < n) w[i] = philox(A.seed, static_cast<uint32_t>(j), A.t, kStep, 0);
+        else w[i] = {0u, 0u, 0u, 0u};
+    }
+    if (resample) {
+        PrevCdf<R> P{static_cast<const R*>(A.c_in), A.tiles_in,
+                     A.scan == kScanTiles ? A.ab_in : nullptr, A.tot_in->M, A.tot_in->S, n, TS};
+        const bool ok = (P.S > 0.0) && isfinite(P.S) && isfinite(P.M);
+        if (!ok) {
+            if (tid == 0) atomicOr(&A.st->flags, kDegenerate);
+        } else {
+            double u_sys = 0.0;
+            if (A.scheme == kSystematicScheme)
+                u_sys = unit64(philox(A.seed, 0, A.t, kSystematic, 0).w0);
+            double u[IPT];
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+                u[i] = resample_uniform(A.scheme, j, n, w[i].w0, u_sys);
+            }
+            const int64_t jlast = min(j0 + TS, n) - 1;
+            const int strategy = A.strategy;
+            if (n <= WIN && strategy != kBinary) {
+                // the whole CDF fits one LDS window
+                stage_window<BLOCK>(P, 0, static_cast<int>(n), -INFINITY, sm.q, sm.ta, sm.tb, sm.red);
+                if (strategy == kCutpoint) build_cutpoints<BLOCK>(sm.q, static_cast<int>(n), sm.cut);
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    int k;
+                    if (strategy == kCutpoint) {
+                        k = cutpoint_draw(sm.q, sm.cut, static_cast<int>(n), u[i]);
+                    } else {
+                        k = lds_lower_bound(sm.q, static_cast<int>(n), u[i]);
+                        if (k > n - 1) k = static_cast<int>(n - 1);
+                    }
+                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+                    if (j < n) anc[i] = k;
+                }
+                __syncthreads();
+            } else if (strategy == kMerge) {
+                // sorted uniforms: the tile's ancestors lie in [a(u_first), a(u_last)].
+                // With the tile-scan table, the hints bound them to the source
+                // tiles of CDF positions j0/N and (j0+TS)/N (one tile of slack
+                // either side for rounding); otherwise search the whole CDF.
+                int64_t lo_b = 0, hi_b = n - 1;
+                const bool indexed = A.scan == kScanTiles;
+                if (wave == 0 || wave == 1) {
+                    const int64_t js = wave == 0 ? j0 : jlast;
+                    const double us = resample_uniform(
+                        A.scheme, js, n,
+                        philox(A.seed, static_cast<uint32_t>(js), A.t, kStep, 0).w0, u_sys);
+                    int64_t a;
+                    if (indexed) {
+                        // the hint names the source tile of CDF position js/N;
+                        // its segment samples bracket u to one segment
+                        constexpr int SEG = TS / kSegments;
+                        const int64_t tmax = A.num_tiles - 1;
+                        const int64_t h = min(max(int64_t(A.hint_in[tile + wave]), int64_t(0)), tmax);
+                        double ta, tb;
+                        P.tile_ab(h, ta, tb);
+                        const R* samp = static_cast<const R*>(A.samp_in);
+                        const double qs = fma(static_cast<double>(samp[h * kSegments + lane]), tb, ta);
+                        const uint64_t mask = __ballot(qs >= us);
+                        const int f = mask ? __ffsll(static_cast<long long>(mask)) - 1 : kSegments;
+                        if (wave == 0) {
+                            // every segment before f ends below u_first
+                            a = h * TS + static_cast<int64_t>(f) * SEG;
+                        } else {
+                            // segment f ends at or above u_last
+                            a = mask ? h * TS + static_cast<int64_t>(f + 1) * SEG - 1
+                                     : (h + 2) * TS - 1;
+                        }
+                        a = min(max(a, int64_t(0)), n - 1);
+                    } else {
+                        a = wave_search(P, us, int64_t(0), n - 1);
+                    }
+                    if (lane == 0) {
+                        if (wave == 0) sm.lo = a; else sm.hi = a;
+                    }
+                }
+                __syncthreads();
+                // (a_hi < a_lo only if the CDF were decreasing; keep one window)
+                const int64_t a_lo = sm.lo, a_hi = max(sm.hi, sm.lo);
+                uint32_t pending = 0;
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+                    if (j < n) pending |= 1u << i;
+                }
+                double floor = -INFINITY;
+                for (int64_t w0 = a_lo; w0 <= a_hi; w0 += WIN) {
+                    const int cnt = static_cast<int>(min(static_cast<int64_t>(WIN), a_hi - w0 + 1));
+                    stage_window<BLOCK>(P, w0, cnt, floor, sm.q, sm.ta, sm.tb, sm.red);
+                    const bool last = (w0 + cnt - 1 == a_hi);
+                    const double top = sm.q[cnt - 1];
+                    const bool first = (w0 == a_lo);
+#pragma unroll
+                    for (int i = 0; i < IPT; ++i) {
+                        if ((pending >> i) & 1u) {
+                            if (last || u[i] <= top) {
+                                int64_t k;
+                                if (first && a_lo > 0 && u[i] <= sm.q[0] && P.at(a_lo - 1) >= u[i]) {
+                                    // the bracket was too high (rounding): exact search below
+                                    k = thread_search(P, u[i], int64_t(0), a_lo - 1);
+                                } else if (u[i] > top && a_hi < n - 1) {
+                                    // above the bracket: exact search beyond it
+                                    k = thread_search(P, u[i], a_hi + 1, n - 1);
+                                } else {
+                                    int kk = lds_lower_bound(sm.q, cnt, u[i]);
+                                    if (kk > cnt - 1) kk = cnt - 1;
+                                    k = w0 + kk;
+                                }
+                                anc[i] = static_cast<int32_t>(k);
+                                pending &= ~(1u << i);
+                            }
+                        }
+                    }
+                    floor = top;
+                    __syncthreads();
+                }
+            } else {
+                // bisection per slot over the tiled CDF
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+                    if (j < n) anc[i] = static_cast<int32_t>(thread_search(P, u[i], 0, n - 1));
+                }
+            }
+        }
+    }
+
+    // ---------------------------------------------------------- 2. propagate
+    const ModelParams& p = A.p;
+    const R* rin = static_cast<const R*>(A.rec_in);
+    R* rout = static_cast<R*>(A.rec_out);
+    R lw[IPT];
+    // moment partials in the weights' precision: weighted ones relative to
+    // the thread's running max (rescaled when it grows), equal-weight ones
+    // as plain sums; folded into double precision across the tile below
+    using M = Math<R>;
+    R pm = R(-INFINITY), pe = R(0), pe2 = R(0);
+    R pg[NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) pg[k] = R(0);
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+        lw[i] = R(-INFINITY);
+        if (j < n) {
+            const int64_t a = anc[i];
+            R z[F], zn[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) z[f] = rin[f * A.pitch + a];
+            R g[NG];
+            if (propagate) {
+                MD::template propagate<R>(p, A.seed, static_cast<uint32_t>(j), A.t, A.y_prop, w[i],
+                                          z, zn, g);
+#pragma unroll
+                for (int f = 0; f < F; ++f) rout[f * A.pitch + j] = zn[f];
+            } else {
+#pragma unroll
+                for (int f = 0; f < F; ++f) zn[f] = z[f];
+                MD::template terms<R>(p, A.t, zn, g);
+            }
+            if (weight) lw[i] = MD::template logw<R>(p, zn, A.y_weight);
+            if (A.anc_out) A.anc_out[j] = anc[i];
+            if (weighted_mom) {
+                const R l = lw[i];
+                if (l > pm) {
+                    const R sc = M::exp(pm - l);
+                    pe *= sc;
+                    pe2 *= sc * sc;
+#pragma unroll
+                    for (int k = 0; k < NG; ++k) pg[k] *= sc;
+                    pm = l;
+                }
+                const R e = (l == R(-INFINITY)) ? R(0) : M::exp(l - pm);
+                pe += e;
+                pe2 += e * e;
+#pragma unroll
+                for (int k = 0; k < NG; ++k) pg[k] += e * g[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < NG; ++k) pg[k] += g[k];
+                pe += R(1);
+            }
+        }
+    }
+
+    // ---------------------------------------------------------- moment partials
+    {
+        // combine the threads' partials in a fixed order (deterministic)
+        const double tm = static_cast<double>(pm);
+        double m = weighted_mom ? wave_max(tm) : 0.0;
+        const double sc = weighted_mom ? (tm == -INFINITY ? 0.0 : exp(tm - m)) : 1.0;
+        const double v_e = wave_sum(static_cast<double>(pe) * sc);
+        const double v_e2 = wave_sum(static_cast<double>(pe2) * sc * sc);
+        double v_g[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) v_g[k] = wave_sum(static_cast<double>(pg[k]) * sc);
+        if (lane == 0) {
+            double* r = sm.red + wave * 16;
+            r[0] = m;
+            r[1] = v_e;
+            r[2] = v_e2;
+#pragma unroll
+            for (int k = 0; k < NG; ++k) r[3 + k] = v_g[k];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double Mx = -INFINITY;
+            if (weighted_mom)
+                for (int q = 0; q < NW; ++q) Mx = fmax(Mx, sm.red[q * 16]);
+            double out[3 + NG];
+            for (int k = 0; k < 3 + NG; ++k) out[k] = 0.0;
+            for (int q = 0; q < NW; ++q) {
+                const double* r = sm.red + q * 16;
+                const double f = weighted_mom ? (r[0] == -INFINITY ? 0.0 : exp(r[0] - Mx)) : 1.0;
+                out[1] += r[1] * f;
+                out[2] += r[2] * f * f;
+                for (int k = 0; k < NG; ++k) out[3 + k] += r[3 + k] * f;
+            }
+            out[0] = weighted_mom ? Mx : 0.0;
+            double* dst = A.partials + static_cast<int64_t>(tile) * kPartialStride;
+            for (int k = 0; k < 3 + NG; ++k) dst[k] = out[k];
+        }
+        __syncthreads();
+    }
+
+    if (!weight) return;
+
+    // ---------------------------------------------------------- 3. tile CDF
+    double mloc = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) mloc = fmax(mloc, static_cast<double>(lw[i]));
+    mloc = wave_max(mloc);
+    if (lane == 0) sm.red[wave] = mloc;
+    __syncthreads();
+    double mb = -INFINITY;
+    for (int q = 0; q < NW; ++q) mb = fmax(mb, sm.red[q]);
+    // e_k = exp(l_k - m_b) in the weights' precision, staged in slot order
+    const R mbr = static_cast<R>(mb);
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const R l = lw[i];
+        const double e = (l == R(-INFINITY) || mb == -INFINITY)
+                             ? 0.0
+                             : static_cast<double>(Math<R>::exp(l - mbr));
+        sm.q[i * BLOCK + tid] = e;
+    }
+    __syncthreads();
+    // blocked scan: thread owns IPT consecutive slots
+    double v[IPT];
+    double run = 0.0;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        run += sm.q[tid * IPT + i];
+        v[i] = run;
+    }
+    const double tincl = wave_incl_sum(run);
+    if (lane == kWave - 1) sm.red[NW + wave] = tincl;
+    __syncthreads();
+    double base = 0.0;
+    for (int q = 0; q < wave; ++q) base += sm.red[NW + q];
+    double total = 0.0;
+    for (int q = 0; q < NW; ++q) total += sm.red[NW + q];
+    double texcl = __shfl_up(tincl, 1, kWave);
+    if (lane == 0) texcl = 0.0;
+    base += texcl;
+    // back to slot order through LDS, so that the stores are coalesced;
+    // single precision rounds toward zero so that a tile's last prefix never
+    // exceeds the tile total the scan uses
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const double cval = base + v[i];
+        sm.q[tid * IPT + i] = sizeof(R) == 4 ? static_cast<double>(__double2float_rz(cval)) : cval;
+    }
+    __syncthreads();
+    if (!lookback && tid < kSegments) {
+        // segment samples of this tile's prefix (the last valid element for
+        // segments that run past N)
+        constexpr int SEG = TS / kSegments;
+        int64_t pos = static_cast<int64_t>(tid + 1) * SEG - 1;
+        if (j0 + pos > n - 1) pos = n - 1 - j0;
+        static_cast<R*>(A.samp_out)[static_cast<int64_t>(tile) * kSegments + tid] =
+            static_cast<R>(sm.q[pos]);
+    }
+    R* cout = static_cast<R*>(A.c_out);
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+        if (j < n) cout[j] = static_cast<R>(sm.q[i * BLOCK + tid]);
+    }
+    const Agg mine{mb, mb == -INFINITY ? 0.0 : total};
+
+    if (!lookback) {
+        // tile scan: publish the tile's (max, sum); k_scan_tiles does the rest
+        if (tid == 0) {
+            A.agg_out[2 * static_cast<int64_t>(tile)] = mine.m;
+            A.agg_out[2 * static_cast<int64_t>(tile) + 1] = mine.s;
+        }
+        return;
+    }
+
+    // ---------------------------------------------------------- 4. look-back
+    if (wave == 0) {
+        const uint32_t epoch = A.epoch;
+        uint64_t* st = A.status;
+        if (lane == 0) put_agg(st + static_cast<int64_t>(tile) * kStatusWords, epoch, mine);
+        // each lane covers kLookPer consecutive predecessors (nearest first),
+        // so one round reads 64 * kLookPer tiles and stops at the nearest
+        // one that has published its inclusive prefix
+        Agg acc = agg_identity();
+        if (tile > 0) {
+            int64_t top = static_cast<int64_t>(tile) - 1;
+            while (true) {
+                Agg part = agg_identity();
+                bool has_incl = false;
+#pragma unroll
+                for (int p = 0; p < kLookPer; ++p) {
+                    if (has_incl) break;
+                    const int64_t idx = top - static_cast<int64_t>(lane) * kLookPer - p;
+                    Agg val = agg_identity();
+                    bool incl = true;  // before tile 0: the inclusive identity
+                    if (idx >= 0) {
+                        const uint64_t* s = st + idx * kStatusWords;
+                        while (true) {
+                            if (get_agg(s + 4, epoch, val)) { incl = true; break; }
+                            if (get_agg(s, epoch, val)) { incl = false; break; }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    part = agg_combine(val, part);
+                    has_incl = incl;
+                }
+                const uint64_t incl_mask = __ballot(has_incl);
+                const int stop = incl_mask ? __ffsll(static_cast<long long>(incl_mask)) - 1 : kWave;
+                const Agg wsum = wave_agg(lane <= stop ? part : agg_identity());
+                acc = agg_combine(wsum, acc);
+                if (incl_mask) break;
+                top -= static_cast<int64_t>(kWave) * kLookPer;
+            }
+        }
+        const Agg incl = agg_combine(acc, mine);
+        if (lane == 0) {
+            put_agg(st + static_cast<int64_t>(tile) * kStatusWords + 4, epoch, incl);
+            A.tiles_out[tile] = TileInfo{acc.m, acc.s, mine.m, mine.s};
+            if (tile == static_cast<uint32_t>(A.num_tiles - 1)) {
+                A.tot_out->M = incl.m;
+                A.tot_out->S = incl.s;
+                const bool ok = (incl.s > 0.0) && isfinite(incl.s) && isfinite(incl.m);
+                if (!ok) atomicOr(&A.st->flags, kDegenerate);
+                A.st->loglik += incl.m + log(incl.s / static_cast<double>(n));
+                // every ticket of this launch has been handed out
+                __hip_atomic_store(&A.st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ tile scan
+// One work-group of 1024 threads turns the tiles' (m_b, s_b) into
+//   A_b = sum_{b' < b} s_b' e^{m_b' - M} / S  (non-decreasing),
+//   B_b = e^{m_b - M} / S,
+// with M = max_b m_b and S = sum_b s_b e^{m_b - M}, in a fixed order (so the
+// result does not depend on timing); adds M + log(S / n) to the
+// log-likelihood; and writes hint[h] = the tile whose range [A_b, A_{b+1})
+// holds the CDF position h * ts / n, for h = 0..tiles, where the next
+// cycle's tile h starts its search for sorted uniforms.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const double* agg, int32_t num_tiles,
+                                                           int64_t n, int32_t ts, TileAB* ab,
+                                                           int32_t* hint, Totals* tot,
+                                                           DevState* st) {
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ double s_m[NW], s_s[NW], s_top[NW];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int T = num_tiles;
+    const int per = (T + kScanBlock - 1) / kScanBlock;
+    const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
+    // 1. each thread folds its chunk
+    Agg part = agg_identity();
+    for (int b = b0; b < b1; ++b) part = agg_combine(part, Agg{agg[2 * b], agg[2 * b + 1]});
+    // 2. exclusive scan of the chunk aggregates: Kogge-Stone in the wave,
+    //    then the waves in order
+    Agg incl = part;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        Agg o{__shfl_up(incl.m, off, kWave), __shfl_up(incl.s, off, kWave)};
+        if (lane >= off) incl = agg_combine(o, incl);
+    }
+    if (lane == kWave - 1) {
+        s_m[wave] = incl.m;
+        s_s[wave] = incl.s;
+    }
+    __syncthreads();
+    Agg wbase = agg_identity(), total = agg_identity();
+    for (int q = 0; q < NW; ++q) {
+        if (q == wave) wbase = total;
+        total = agg_combine(total, Agg{s_m[q], s_s[q]});
+    }
+    Agg excl{__shfl_up(incl.m, 1, kWave), __shfl_up(incl.s, 1, kWave)};
+    if (lane == 0) excl = agg_identity();
+    excl = agg_combine(wbase, excl);
+    const double M = total.m, S = total.s;
+    const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
+    // 3. normalised affine constants, made non-decreasing (running max over
+    //    the chunk, then over the chunks' maxima)
+    Agg run = excl;
+    double amax = -INFINITY;
+    for (int b = b0; b < b1; ++b) {
+        const double mb = agg[2 * b], sb = agg[2 * b + 1];
+        double a = (run.m == -INFINITY || !ok) ? 0.0 : run.s * exp(run.m - M) / S;
+        amax = fmax(amax, a);
+        ab[b] = TileAB{amax, (mb == -INFINITY || !ok) ? 0.0 : exp(mb - M) / S};
+        run = agg_combine(run, Agg{mb, sb});
+    }
+    const double top = wave_incl_max(amax);
+    if (lane == kWave - 1) s_top[wave] = top;
+    __syncthreads();
+    double carry = -INFINITY;
+    for (int q = 0; q < wave; ++q) carry = fmax(carry, s_top[q]);
+    double ex = __shfl_up(top, 1, kWave);
+    if (lane == 0) ex = -INFINITY;
+    carry = fmax(carry, ex);
+    if (carry > -INFINITY) {
+        for (int b = b0; b < b1; ++b) {
+            if (ab[b].a < carry) ab[b].a = carry;
+        }
+    }
+    __syncthreads();
+    // 4. search hints: tile b owns the output tiles h with
+    //    ceil(A_b n / ts) <= h < ceil(A_{b+1} n / ts); tile 0 starts at h = 0
+    //    and the last tile runs to h = tiles.  Every tile reads A_b and
+    //    A_{b+1} from the same stored table, so the ranges partition 0..tiles.
+    const double scale = static_cast<double>(n) / static_cast<double>(ts);
+    auto first_h = [&](int b) -> int64_t {
+        if (b == 0) return 0;
+        if (b >= T) return static_cast<int64_t>(T) + 1;
+        const double v = ceil(ab[b].a * scale);
+        return v > static_cast<double>(T) ? static_cast<int64_t>(T) : static_cast<int64_t>(v);
+    };
+    for (int b = b0; b < b1; ++b) {
+        const int64_t h0 = first_h(b), h1 = first_h(b + 1);
+        for (int64_t h = h0; h < h1; ++h) hint[h] = b;
+    }
+    if (tid == 0) {
+        tot->M = M;
+        tot->S = S;
+        if (!ok) atomicOr(&st->flags, kDegenerate);
+        st->loglik += M + log(S / static_cast<double>(n));
+    }
+}
+
+// ------------------------------------------------------------ initial particles
+template <int MODEL, typename R, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_init(StepArgs A) {
+    using MD = ModelDef<MODEL>;
+    constexpr int F = MD::F, NG = MD::NG;
+    constexpr int TS = BLOCK * IPT, NW = BLOCK / kWave;
+    __shared__ double red[NW * 16];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * TS;
+    R* rout = static_cast<R*>(A.rec_out);
+    double pg[NG];
+    for (int k = 0; k < NG; ++k) pg[k] = 0.0;
+    double cnt = 0.0;
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+        if (j < A.n) {
+            R z[F];
+            MD::template init<R>(A.p, A.seed, static_cast<uint32_t>(j), z);
+            for (int f = 0; f < F; ++f) rout[f * A.pitch + j] = z[f];
+            R g[NG];
+            MD::template terms<R>(A.p, 0, z, g);
+            for (int k = 0; k < NG; ++k) pg[k] += static_cast<double>(g[k]);
+            cnt += 1.0;
+            if (A.anc_out) A.anc_out[j] = static_cast<int32_t>(j);
+        }
+    }
+    // status words of this tile start invalid; scalars start at zero
+    if (tid < kStatusWords) A.status[static_cast<int64_t>(blockIdx.x) * kStatusWords + tid] = 0;
+    if (blockIdx.x == 0 && tid == 0) {
+        A.st->loglik = 0.0;
+        A.st->ticket = 0;
+        A.st->flags = 0;
+    }
+    double vc = wave_sum(cnt);
+    double vg[NG];
+    for (int k = 0; k < NG; ++k) vg[k] = wave_sum(pg[k]);
+    if (lane == 0) {
+        red[wave * 16 + 1] = vc;
+        for (int k = 0; k < NG; ++k) red[wave * 16 + 3 + k] = vg[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double* dst = A.partials + static_cast<int64_t>(blockIdx.x) * kPartialStride;
+        double out[3 + NG];
+        for (int k = 0; k < 3 + NG; ++k) out[k] = 0.0;
+        for (int q = 0; q < NW; ++q) {
+            out[1] += red[q * 16 + 1];
+            for (int k = 0; k < NG; ++k) out[3 + k] += red[q * 16 + 3 + k];
+        }
+        for (int k = 0; k < 3 + NG; ++k) dst[k] = out[k];
+    }
+}
+
+// ------------------------------------------------------------ moment reduction
+// One work-group folds the per-tile partials in a fixed order and writes the
+// model's moment vector to st->moments.
+template <int MODEL>
+__global__ __launch_bounds__(256) void k_moments(const double* partials, int32_t num_tiles,
+                                                 int64_t n, int32_t weighted, uint32_t t,
+                                                 ModelParams p, DevState* st) {
+    using MD = ModelDef<MODEL>;
+    constexpr int NG = MD::NG, NW = 256 / kWave;
+    __shared__ double red[NW * 16];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    double M = -INFINITY;
+    if (weighted)
+        for (int b = tid; b < num_tiles; b += 256) M = fmax(M, partials[b * kPartialStride]);
+    M = wave_max(M);
+    if (lane == 0) red[wave] = M;
+    __syncthreads();
+    M = -INFINITY;
+    for (int q = 0; q < NW; ++q) M = fmax(M, red[q]);
+    __syncthreads();
+    double acc[2 + NG];
+    for (int k = 0; k < 2 + NG; ++k) acc[k] = 0.0;
+    for (int b = tid; b < num_tiles; b += 256) {
+        const double* r = partials + static_cast<int64_t>(b) * kPartialStride;
+        const double f = weighted ? (r[0] == -INFINITY ? 0.0 : exp(r[0] - M)) : 1.0;
+        acc[0] += r[1] * f;
+        acc[1] += r[2] * f * f;
+        for (int k = 0; k < NG; ++k) acc[2 + k] += r[3 + k] * f;
+    }
+    for (int k = 0; k < 2 + NG; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0)
+        for (int k = 0; k < 2 + NG; ++k) red[wave * 16 + k] = acc[k];
+    __syncthreads();
+    if (tid == 0) {
+        double s[2 + NG];
+        for (int k = 0; k < 2 + NG; ++k) {
+            s[k] = 0.0;
+            for (int q = 0; q < NW; ++q) s[k] += red[q * 16 + k];
+        }
+        const double W = weighted ? s[0] : static_cast<double>(n);
+        double out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const double ex = s[2] / W, exx = s[3] / W;
+        out[0] = ex;
+        out[1] = exx - ex * ex;
+        const double ess = weighted ? s[0] * s[0] / s[1] : static_cast<double>(n);
+        if (MODEL == kLLPF || MODEL == kSVPF) {
+            out[2] = ess;
+        } else if (MODEL == kLLPL) {
+            const double av = p.a_v + 0.5 * t, aw = p.a_w + 0.5 * t;
+            out[2] = s[4] / W;
+            out[3] = s[5] / W;
+            out[4] = s[6] / W / (av - 1.0);
+            out[5] = s[7] / W / (aw - 1.0);
+        } else {
+            out[2] = s[4] / W;
+            out[3] = s[5] / W;
+            out[4] = s[6] / W;
+            out[5] = ess;
+            out[6] = s[7] / W;
+        }
+        for (int k = 0; k < 8; ++k) st->moments[k] = out[k];
+    }
+}
+
+// ------------------------------------------------------------ search test surface
+// anc[j] = min{k : q(k) >= u[j]} (n-1 if none) for a plain double CDF.
+__global__ void k_search_binary(PlainCdf cdf, const double* u, int64_t m, int32_t* anc) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < m) anc[j] = static_cast<int32_t>(thread_search(cdf, u[j], 0, cdf.n - 1));
+}
+
+// Parallelized cut-point search (Section 3.2): thread j writes its own index
+// into the table entries it owns, L_{j-1}+1 .. L_j (1-based), L_j = ceil(n q(j)).
+__global__ void k_cutpoint_build(const double* q, int64_t n, int32_t* table) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double dn = static_cast<double>(n);
+    const double cj = ceil(dn * q[j]);
+    const int64_t Lj = cj < 0.0 ? 0 : (cj > dn ? n : static_cast<int64_t>(cj));
+    int64_t Lp = 0;
+    if (j > 0) {
+        const double cp = ceil(dn * q[j - 1]);
+        Lp = cp < 0.0 ? 0 : (cp > dn ? n : static_cast<int64_t>(cp));
+    }
+    const int64_t top = (j == n - 1) ? n : Lj;
+    for (int64_t k = top; k > Lp; --k) table[k - 1] = static_cast<int32_t>(j);
+}
+
+// Parallelized cut-point method (Section 3.2): one thread per uniform starts
+// at I_{ceil(n u)} and climbs; after 16 climbs it bisects above its position.
+__global__ void k_cutpoint_draw(PlainCdf cdf, const int32_t* table, const double* u, int64_t m,
+                                int32_t* anc) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int64_t n = cdf.n;
+    const double uj = u[j];
+    const double ce = ceil(static_cast<double>(n) * uj);
+    const int64_t e = ce < 1.0 ? 1 : (ce > static_cast<double>(n) ? n : static_cast<int64_t>(ce));
+    int64_t k = table[e - 1];
+    for (int c = 0; c < 16 && k < n - 1 && uj > cdf.q[k]; ++c) ++k;
+    if (k < n - 1 && uj > cdf.q[k]) k = thread_search(cdf, uj, k + 1, n - 1);
+    anc[j] = static_cast<int32_t>(k);
+}
+
+// Merge of a tile of (preferably sorted) uniforms against the CDF staged in
+// LDS: the tile's answers lie in [a(min u), a(max u)], walked in windows.
+template <int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_search_merge(PlainCdf cdf, const double* u, int64_t m,
+                                                        int32_t* anc) {
+    constexpr int TS = BLOCK * IPT, WIN = 2 * TS, NW = BLOCK / kWave;
+    __shared__ double s_q[WIN];
+    __shared__ double s_red[NW * 2];
+    __shared__ int64_t s_lo, s_hi;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * TS;
+    const int64_t n = cdf.n;
+    double uu[IPT];
+    double umin = INFINITY, umax = -INFINITY;
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+        uu[i] = j < m ? u[j] : 0.0;
+        if (j < m) {
+            umin = fmin(umin, uu[i]);
+            umax = fmax(umax, uu[i]);
+        }
+    }
+    umin = -wave_max(-umin);
+    umax = wave_max(umax);
+    if (lane == 0) {
+        s_red[wave] = umin;
+        s_red[NW + wave] = umax;
+    }
+    __syncthreads();
+    umin = INFINITY;
+    umax = -INFINITY;
+    for (int q = 0; q < NW; ++q) {
+        umin = fmin(umin, s_red[q]);
+        umax = fmax(umax, s_red[NW + q]);
+    }
+    if (wave < 2) {
+        const int64_t a = wave_search(cdf, wave == 0 ? umin : umax, 0, n - 1);
+        if (lane == 0) {
+            if (wave == 0) s_lo = a; else s_hi = a;
+        }
+    }
+    __syncthreads();
+    const int64_t a_lo = s_lo, a_hi = max(s_hi, s_lo);
+    uint32_t pending = 0;
+    for (int i = 0; i < IPT; ++i)
+        if (j0 + static_cast<int64_t>(i) * BLOCK + tid < m) pending |= 1u << i;
+    for (int64_t w0 = a_lo; w0 <= a_hi; w0 += WIN) {
+        const int cnt = static_cast<int>(min(static_cast<int64_t>(WIN), a_hi - w0 + 1));
+        for (int k = tid; k < cnt; k += BLOCK) s_q[k] = cdf.q[w0 + k];
+        __syncthreads();
+        const bool last = (w0 + cnt - 1 == a_hi);
+        const double top = s_q[cnt - 1];
+        for (int i = 0; i < IPT; ++i) {
+            if ((pending >> i) & 1u) {
+                if (last || uu[i] <= top) {
+                    int k = lds_lower_bound(s_q, cnt, uu[i]);
+                    if (k > cnt - 1) k = cnt - 1;
+                    anc[j0 + static_cast<int64_t>(i) * BLOCK + tid] = static_cast<int32_t>(w0 + k);
+                    pending &= ~(1u << i);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Non-decreasing and finite check of a plain CDF: sets *bad when violated.
+__global__ void k_check_cdf(const double* q, int64_t n, int32_t* bad) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double v = q[k];
+    bool b = !isfinite(v);
+    if (k > 0 && q[k - 1] > v) b = true;
+    if (b) atomicOr(bad, 1);
+}
+
+}  // namespace pf
+
+// ------------------------------------------------------------ launchers
+namespace pf {
+
+using StepFn = void (*)(StepArgs);
+
+template <int MODEL, typename R, int IPT>
+static hipError_t launch_step_t(const StepArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<MODEL, R, 256, IPT>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <int MODEL, typename R, int IPT>
+static hipError_t launch_init_t(const StepArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_init<MODEL, R, 256, IPT>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int MODEL, typename R>
+static hipError_t launch_step_m(const StepArgs& a, int ipt, int grid, hipStream_t s, bool init) {
+    switch (ipt) {
+    case 1: return init ? launch_init_t<MODEL, R, 1>(a, grid, s) : launch_step_t<MODEL, R, 1>(a, grid, s);
+    case 2: return init ? launch_init_t<MODEL, R, 2>(a, grid, s) : launch_step_t<MODEL, R, 2>(a, grid, s);
+    case 4: return init ? launch_init_t<MODEL, R, 4>(a, grid, s) : launch_step_t<MODEL, R, 4>(a, grid, s);
+    case 8: return init ? launch_init_t<MODEL, R, 8>(a, grid, s) : launch_step_t<MODEL, R, 8>(a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int model, bool fp64, int ipt, const StepArgs& a, int grid, hipStream_t s,
+                       bool init) {
+    switch (model) {
+    case kLLPF: return fp64 ? launch_step_m<kLLPF, double>(a, ipt, grid, s, init)
+                            : launch_step_m<kLLPF, float>(a, ipt, grid, s, init);
+    case kLLPL: return fp64 ? launch_step_m<kLLPL, double>(a, ipt, grid, s, init)
+                            : launch_step_m<kLLPL, float>(a, ipt, grid, s, init);
+    case kSVPF: return fp64 ? launch_step_m<kSVPF, double>(a, ipt, grid, s, init)
+                            : launch_step_m<kSVPF, float>(a, ipt, grid, s, init);
+    case kSVPL: return fp64 ? launch_step_m<kSVPL, double>(a, ipt, grid, s, init)
+                            : launch_step_m<kSVPL, float>(a, ipt, grid, s, init);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_scan_tiles(const double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
+                             int32_t* hint, Totals* tot, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, s, agg, num_tiles, n, ts, ab, hint,
+                       tot, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int model, const double* partials, int32_t num_tiles, int64_t n,
+                          int32_t weighted, uint32_t t, const ModelParams& p, DevState* st,
+                          hipStream_t s) {
+    switch (model) {
+    case kLLPF: hipLaunchKernelGGL(k_moments<kLLPF>, dim3(1), dim3(256), 0, s, partials, num_tiles, n, weighted, t, p, st); break;
+    case kLLPL: hipLaunchKernelGGL(k_moments<kLLPL>, dim3(1), dim3(256), 0, s, partials, num_tiles, n, weighted, t, p, st); break;
+    case kSVPF: hipLaunchKernelGGL(k_moments<kSVPF>, dim3(1), dim3(256), 0, s, partials, num_tiles, n, weighted, t, p, st); break;
+    case kSVPL: hipLaunchKernelGGL(k_moments<kSVPL>, dim3(1), dim3(256), 0, s, partials, num_tiles, n, weighted, t, p, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_search(int strategy, const double* q, int64_t n, const double* u, int64_t m,
+                         int32_t* anc, int32_t* table, int32_t* bad, hipStream_t s) {
+    const int tb = 256;
+    hipLaunchKernelGGL(k_check_cdf, dim3((n + tb - 1) / tb), dim3(tb), 0, s, q, n, bad);
+    if (m == 0) return hipGetLastError();
+    PlainCdf cdf{q, n};
+    if (strategy == kBinary) {
+        hipLaunchKernelGGL(k_search_binary, dim3((m + tb - 1) / tb), dim3(tb), 0, s, cdf, u, m, anc);
+    } else if (strategy == kCutpoint) {
+        hipLaunchKernelGGL(k_cutpoint_build, dim3((n + tb - 1) / tb), dim3(tb), 0, s, q, n, table);
+        hipLaunchKernelGGL(k_cutpoint_draw, dim3((m + tb - 1) / tb), dim3(tb), 0, s, cdf, table, u, m, anc);
+    } else {
+        constexpr int IPT = 4;
+        const int64_t grid = (m + 256 * IPT - 1) / (256 * IPT);
+        hipLaunchKernelGGL((k_search_merge<256, IPT>), dim3(grid), dim3(256), 0, s, cdf, u, m, anc);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pf

@@ -27,10 +27,13 @@ def oracle_config(orc, model, n, seed, scheme, fp32):
                            fp32_words=fp32, **PARAMS[model])
 
 
-def pf_config(pf, model, n, seed, scheme, fp32, strategy=0, ipt=0):
+def pf_config(pf, model, n, seed, scheme, fp32, strategy=0, ipt=0, keep_ancestors=True,
+              lookback=False):
+    flags = (pf.FLAG_KEEP_ANCESTORS if keep_ancestors else 0) | (
+        pf.FLAG_LOOKBACK_SCAN if lookback else 0)
     return pf.make_config(MODEL_ID[model], n, seed, scheme=SCHEME_ID[scheme],
                           precision=pf.FP32 if fp32 else pf.FP64, strategy=strategy,
-                          items_per_thread=ipt, **PARAMS[model])
+                          items_per_thread=ipt, flags=flags, **PARAMS[model])
 
 
 def oracle_to_record(orc, model, ocfg, state):
@@ -45,3 +48,24 @@ def oracle_to_record(orc, model, ocfg, state):
     d = np.array([orc.sv_posterior(ocfg, [n[i], S1[i], S11[i], Sy[i], S1y[i], Syy[i]])[6]
                   for i in range(x.size)])
     return np.stack([x, P1 + S1, P2 + S11, eta0a + Sy, eta0b + S1y, d])
+
+
+def record_to_oracle(model, rec, t0):
+    """The library's record (F, N) after t0 steps -> oracle fields (F_oracle, N)."""
+    rec = np.asarray(rec, dtype=np.float64)
+    if model != "sv_pl":
+        return rec
+    p = PARAMS[model]
+    P0, P1, P2 = p["prior_prec"]
+    b0a, b0b = p["prior_mean"]
+    eta0a, eta0b = P0 * b0a + P1 * b0b, P1 * b0a + P2 * b0b
+    quad0 = b0a * eta0a + b0b * eta0b
+    x, L01, L11, e0, e1, d = rec
+    L00 = P0 + t0
+    det = L00 * L11 - L01 * L01
+    m0 = (L11 * e0 - L01 * e1) / det
+    m1 = (L00 * e1 - L01 * e0) / det
+    mlm = m0 * e0 + m1 * e1  # m' Lambda m = eta' Lambda^{-1} eta
+    Syy = 2.0 * (d - p["d_s"]) - quad0 + mlm
+    n = np.full_like(x, float(t0))
+    return np.stack([x, n, L01 - P1, L11 - P2, e0 - eta0a, e1 - eta0b, Syy])

@@ -50,12 +50,14 @@ def test_workspace_bytes_and_validation(pf):
     good = pf.make_config("ll_pl", 1 << 20, 1, scheme=pf.STRATIFIED, a_v=2, b_v=1, a_w=2, b_w=1,
                           x0_var=10)
     nb = pf.workspace_bytes(good)
-    # records (2 x 5 fields x 4 B), CDF (2 x 4 B), ancestors (4 B) per particle
-    assert nb >= (1 << 20) * (40 + 8 + 4)
-    assert nb < (1 << 20) * 64
+    # records (2 x 5 fields x 4 B) and CDF (2 x 4 B) per particle
+    assert (1 << 20) * (40 + 8) <= nb < (1 << 20) * 52
+    keep = pf.make_config("ll_pl", 1 << 20, 1, scheme=pf.STRATIFIED, a_v=2, b_v=1, a_w=2, b_w=1,
+                          x0_var=10, flags=pf.FLAG_KEEP_ANCESTORS)
+    assert pf.workspace_bytes(keep) >= nb + 4 * (1 << 20)  # plus the ancestors
     bad = [
         dict(n=0), dict(n=1 << 31), dict(scheme=7), dict(precision=3), dict(strategy=9),
-        dict(items_per_thread=3), dict(x0_var=-1.0), dict(a_v=0.5),
+        dict(items_per_thread=3), dict(x0_var=-1.0), dict(a_v=0.5), dict(flags=4),
     ]
     for b in bad:
         kw = dict(model="ll_pl", n=1024, seed=1, scheme=pf.STRATIFIED, a_v=2, b_v=1, a_w=2, b_w=1,

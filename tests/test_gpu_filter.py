@@ -31,33 +31,39 @@ def _strategy(pf, name):
 
 
 CASES = [
-    # model, n, scheme, strategy, items_per_thread, T
-    ("ll_pf", 1024, "multinomial", "auto", 0, 100),       # the 1024-particle FP64 workload
-    ("ll_pf", 1500, "multinomial", "cutpoint", 4, 20),
-    ("ll_pf", 3000, "stratified", "merge", 1, 20),
-    ("ll_pf", 3000, "multinomial", "binary", 1, 20),
-    ("ll_pf", 700, "systematic", "merge", 1, 20),
-    ("ll_pl", 3000, "stratified", "merge", 1, 20),
-    ("ll_pl", 1500, "multinomial", "auto", 4, 20),
-    ("ll_pl", 2049, "systematic", "binary", 2, 20),
-    ("sv_pf", 3000, "systematic", "merge", 1, 20),
-    ("sv_pf", 1000, "multinomial", "cutpoint", 4, 20),
-    ("sv_pl", 3000, "systematic", "merge", 1, 20),
-    ("sv_pl", 1777, "stratified", "binary", 2, 20),
-    ("sv_pl", 513, "multinomial", "auto", 1, 20),
+    # model, n, scheme, strategy, items_per_thread, T, scan
+    ("ll_pf", 1024, "multinomial", "auto", 0, 100, "tiles"),   # the 1024-particle FP64 workload
+    ("ll_pf", 1500, "multinomial", "cutpoint", 4, 20, "tiles"),
+    ("ll_pf", 3000, "stratified", "merge", 1, 20, "tiles"),
+    ("ll_pf", 3000, "multinomial", "binary", 1, 20, "tiles"),
+    ("ll_pf", 700, "systematic", "merge", 1, 20, "tiles"),
+    ("ll_pf", 9001, "stratified", "merge", 2, 12, "tiles"),
+    ("ll_pl", 3000, "stratified", "merge", 1, 20, "tiles"),
+    ("ll_pl", 1500, "multinomial", "auto", 4, 20, "tiles"),
+    ("ll_pl", 2049, "systematic", "binary", 2, 20, "tiles"),
+    ("sv_pf", 3000, "systematic", "merge", 1, 20, "tiles"),
+    ("sv_pf", 1000, "multinomial", "cutpoint", 4, 20, "tiles"),
+    ("sv_pl", 3000, "systematic", "merge", 1, 20, "tiles"),
+    ("sv_pl", 1777, "stratified", "binary", 2, 20, "tiles"),
+    ("sv_pl", 513, "multinomial", "auto", 1, 20, "tiles"),
+    ("sv_pl", 20000, "systematic", "merge", 8, 10, "tiles"),
+    ("ll_pf", 3000, "stratified", "merge", 1, 20, "lookback"),
+    ("ll_pl", 2049, "systematic", "binary", 2, 20, "lookback"),
+    ("sv_pl", 3000, "systematic", "merge", 1, 20, "lookback"),
+    ("sv_pf", 9001, "stratified", "merge", 8, 12, "lookback"),
 ]
 
 
-@pytest.mark.parametrize("model,n,scheme,strat,ipt,T", CASES)
-def test_fp64_stepwise_parity(pf, orc, model, n, scheme, strat, ipt, T):
-    print(f"fp64 parity {model} n={n} {scheme} {strat} ipt={ipt} T={T}", flush=True)
+@pytest.mark.parametrize("model,n,scheme,strat,ipt,T,scan", CASES)
+def test_fp64_stepwise_parity(pf, orc, model, n, scheme, strat, ipt, T, scan):
+    print(f"fp64 parity {model} n={n} {scheme} {strat} ipt={ipt} T={T} scan={scan}", flush=True)
     y = C.data(model, T)
     seed = 7
     ocfg = C.oracle_config(orc, model, n, seed, scheme, fp32=False)
     ref = orc.run(ocfg, y, dump=True)
     assert ref["rc"] == 0
     cfg = C.pf_config(pf, model, n, seed, scheme, fp32=False, strategy=_strategy(pf, strat),
-                      ipt=ipt)
+                      ipt=ipt, lookback=(scan == "lookback"))
     f = pf.Filter(cfg)
     lag = 1 if model == "ll_pl" else 0
     for t in range(1, T + 1):
@@ -83,34 +89,80 @@ def _rel_err(a, b, sd):
     return np.abs(a - b) / np.maximum(np.abs(b), sd)
 
 
-@pytest.mark.parametrize("model,n,scheme,T", [
-    ("ll_pl", 1 << 16, "stratified", 100),
-    ("ll_pf", 1 << 16, "stratified", 100),
-    ("sv_pl", 1 << 16, "systematic", 100),
-    ("sv_pf", 1 << 16, "systematic", 100),
-])
-def test_fp32_tolerances(pf, orc, model, n, scheme, T):
-    print(f"fp32 tolerance {model} n={n} {scheme} T={T}", flush=True)
-    y = C.data(model, T)
-    ocfg = C.oracle_config(orc, model, n, 3, scheme, fp32=True)
-    ref = orc.run(ocfg, y)
+FP32_MODELS = [("ll_pl", "stratified"), ("ll_pf", "stratified"), ("sv_pl", "systematic"),
+               ("sv_pf", "systematic")]
+
+
+@pytest.mark.parametrize("model,scheme", FP32_MODELS)
+def test_fp32_one_step_from_common_state(pf, orc, model, scheme):
+    """Single precision against the double-precision oracle over one cycle
+    started from the same particles (the GPU's own state after t0 steps):
+    filtered moments within 1e-4 relative (to max(|m|, sd) for the state),
+    the step's log-likelihood increment within 1e-3, ancestors equal except
+    for the rare slots whose uniform falls within rounding of a CDF value."""
+    n, t0 = 1 << 18, 40
+    print(f"fp32 one step {model} n={n} {scheme} t0={t0}", flush=True)
+    y = C.data(model, t0 + 2)
     cfg = C.pf_config(pf, model, n, 3, scheme, fp32=True)
     f = pf.Filter(cfg)
+    f.step(y[:t0])
+    ll_a = f.loglik()
+    if model == "ll_pl":
+        # scores y_{t0+1} on z_{t0}; the particles are still z_{t0}
+        f.step(y[t0:t0 + 1])
+        ll_inc = f.loglik() - ll_a
+        rec0, _, tt = f.particles()
+        mom = f.moments()          # propagates with y_{t0+1}
+    else:
+        rec0, _, tt = f.particles()
+        f.step(y[t0:t0 + 1])
+        ll_inc = f.loglik() - ll_a
+        mom = f.moments()
+    assert tt == t0
+    rec1, anc1, tt1 = f.particles()
+    f.close()
+    assert tt1 == t0 + 1
+    ocfg = C.oracle_config(orc, model, n, 3, scheme, fp32=True)
+    ref = orc.run(ocfg, y[t0:t0 + 1], dump=True, state0=C.record_to_oracle(model, rec0, t0),
+                  t0=t0, y_prev=y[t0 - 1])
+    want = ref["moments"][0, : mom.size]
+    sd = np.sqrt(want[1])
+    assert _rel_err(mom[0], want[0], sd) <= 1e-4, (mom, want)
+    assert abs(mom[1] - want[1]) <= 1e-4 * want[1]
+    for i in range(2, mom.size):
+        assert abs(mom[i] - want[i]) <= 1e-4 * abs(want[i]), (i, mom[i], want[i])
+    assert abs(ll_inc - ref["loglik"][0]) <= 1e-3, (ll_inc, ref["loglik"][0])
+    flips = np.count_nonzero(anc1 != ref["anc"][0])
+    print("ancestor flips", flips, "of", n)
+    assert flips <= 1e-3 * n
+    same = anc1 == ref["anc"][0]
+    want_rec = C.oracle_to_record(orc, model, ocfg, ref["state"][0]) if model != "sv_pl" else None
+    if want_rec is not None:
+        close = np.isclose(rec1[:, same], want_rec[:, same], rtol=1e-4, atol=1e-5)
+        assert np.count_nonzero(~close) <= 1e-4 * n * rec1.shape[0]
+
+
+@pytest.mark.parametrize("model,scheme", FP32_MODELS)
+def test_fp32_trajectory(pf, orc, model, scheme):
+    """A whole single-precision run against the double-precision oracle:
+    |d loglik| <= 1e-3 T.  The filtered moments of the two runs decorrelate
+    after the first ancestor flips, so they are held to Monte Carlo
+    consistency: within 5% of the filtered standard deviation, several Monte
+    Carlo standard errors of a 2^16-particle filter."""
+    n, T = 1 << 16, 100
+    print(f"fp32 trajectory {model} n={n} {scheme} T={T}", flush=True)
+    y = C.data(model, T)
+    ref = orc.run(C.oracle_config(orc, model, n, 3, scheme, fp32=True), y)
+    f = pf.Filter(C.pf_config(pf, model, n, 3, scheme, fp32=True))
     f.step(y)
     ll = f.loglik()
     mom = f.moments()
     f.close()
     assert abs(ll - ref["loglik"].sum()) <= 1e-3 * T, (ll, ref["loglik"].sum())
     want = ref["moments"][-1, : mom.size]
-    sd = np.sqrt(max(want[1], 1e-300))
-    err = _rel_err(mom[0], want[0], sd)
-    print("loglik", ll, ref["loglik"].sum(), "moments", mom, want, "rel err E x", err)
-    assert err <= 1e-4
-    # parameter means (scale: themselves)
-    others = [i for i in range(2, mom.size) if not (model.endswith("pf") or
-                                                     (model == "sv_pl" and i == 5))]
-    for i in others:
-        assert abs(mom[i] - want[i]) <= 1e-4 * abs(want[i]), (i, mom[i], want[i])
+    sd = np.sqrt(want[1])
+    print("loglik", ll, ref["loglik"].sum(), "moments", mom, want)
+    assert abs(mom[0] - want[0]) <= 0.05 * sd
 
 
 def test_ll_pl_call_pattern_does_not_change_results(pf):
@@ -141,17 +193,24 @@ def test_ll_pl_call_pattern_does_not_change_results(pf):
         np.testing.assert_array_equal(rec, outs[0][2])
 
 
-def test_repeat_runs_are_identical(pf):
+@pytest.mark.parametrize("scan", ["tiles", "lookback"])
+def test_repeat_runs(pf, scan):
+    # the tile scan folds the tiles in a fixed order: runs are bit-identical;
+    # the look-back's association depends on timing (differences of ulps)
     y = C.data("sv_pl", 30)
     res = []
     for _ in range(2):
-        cfg = C.pf_config(pf, "sv_pl", 100000, 5, "systematic", fp32=True)
+        cfg = C.pf_config(pf, "sv_pl", 100000, 5, "systematic", fp32=True,
+                          lookback=(scan == "lookback"))
         f = pf.Filter(cfg)
         f.step(y)
         res.append((f.loglik(), f.particles()[0]))
         f.close()
-    assert abs(res[0][0] - res[1][0]) < 1e-9
-    np.testing.assert_array_equal(res[0][1], res[1][1])
+    if scan == "tiles":
+        assert res[0][0] == res[1][0]
+        np.testing.assert_array_equal(res[0][1], res[1][1])
+    else:
+        assert abs(res[0][0] - res[1][0]) < 1e-9
 
 
 def test_errors(pf):
