@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--workload", default="ll_pl_2p20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--items-per-thread", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="instead of the filter, copy MIB mebibytes device to device (a plain "
+                         "copy kernel of known size, to scale the profiler's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs one filter per GPU and has no "
@@ -98,6 +101,17 @@ def main():
 
     import torch
     from paper_1212_1639_amd import pf
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps or 3)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": nbytes,
+                          "copies": max(1, args.steps or 3)}), flush=True)
+        return
 
     w = WORKLOADS[args.workload]
     K = args.steps or w["T"]

@@ -293,12 +293,16 @@ __device__ __forceinline__ int cutpoint_draw(const double* s_q, const int* s_cut
     return k;
 }
 
+// Resampling uniform of slot j (Section 3.1), in double precision.  With
+// EXACT the stratum position is divided by N (correctly rounded, as the
+// double-precision reference does); otherwise it is multiplied by 1/N
+// (within an ulp; exact when N is a power of two).
+template <bool EXACT>
 __device__ __forceinline__ double resample_uniform(int32_t scheme, int64_t j, int64_t n,
-                                                   uint32_t w0, double u_sys) {
+                                                   double inv_n, uint32_t w0, double u_sys) {
     if (scheme == kMultinomial) return unit64(w0);
-    if (scheme == kStratified)
-        return (static_cast<double>(j) + unit64(w0)) / static_cast<double>(n);
-    return (static_cast<double>(j) + u_sys) / static_cast<double>(n);
+    const double pos = static_cast<double>(j) + (scheme == kStratified ? unit64(w0) : u_sys);
+    return EXACT ? pos / static_cast<double>(n) : pos * inv_n;
 }
 
 // ------------------------------------------------------------ shared memory
@@ -365,6 +369,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
         if (!ok) {
             if (tid == 0) atomicOr(&A.st->flags, kDegenerate);
         } else {
+            constexpr bool kExact = sizeof(R) == 8;
+            const double inv_n = 1.0 / static_cast<double>(n);
             double u_sys = 0.0;
             if (A.scheme == kSystematicScheme)
                 u_sys = unit64(philox(A.seed, 0, A.t, kSystematic, 0).w0);
@@ -372,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                u[i] = resample_uniform(A.scheme, j, n, w[i].w0, u_sys);
+                u[i] = resample_uniform<kExact>(A.scheme, j, n, inv_n, w[i].w0, u_sys);
             }
             const int64_t jlast = min(j0 + TS, n) - 1;
             const int strategy = A.strategy;
@@ -402,8 +408,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
                 const bool indexed = A.scan == kScanTiles;
                 if (wave == 0 || wave == 1) {
                     const int64_t js = wave == 0 ? j0 : jlast;
-                    const double us = resample_uniform(
-                        A.scheme, js, n,
+                    const double us = resample_uniform<kExact>(
+                        A.scheme, js, n, inv_n,
                         philox(A.seed, static_cast<uint32_t>(js), A.t, kStep, 0).w0, u_sys);
                     int64_t a;
                     if (indexed) {
@@ -500,19 +506,20 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     for (int k = 0; k < NG; ++k) pg[k] = R(0);
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+        // slot and ancestor indices fit 32 bits (N < 2^31): uniform per-field
+        // base pointers plus a 32-bit offset keep the address math scalar
+        const uint32_t j = static_cast<uint32_t>(j0) + static_cast<uint32_t>(i * BLOCK + tid);
         lw[i] = R(-INFINITY);
-        if (j < n) {
-            const int64_t a = anc[i];
+        if (static_cast<int64_t>(j) < n) {
+            const uint32_t a = static_cast<uint32_t>(anc[i]);
             R z[F], zn[F];
 #pragma unroll
-            for (int f = 0; f < F; ++f) z[f] = rin[f * A.pitch + a];
+            for (int f = 0; f < F; ++f) z[f] = (rin + f * A.pitch)[a];
             R g[NG];
             if (propagate) {
-                MD::template propagate<R>(p, A.seed, static_cast<uint32_t>(j), A.t, A.y_prop, w[i],
-                                          z, zn, g);
+                MD::template propagate<R>(p, A.seed, j, A.t, A.y_prop, w[i], z, zn, g);
 #pragma unroll
-                for (int f = 0; f < F; ++f) rout[f * A.pitch + j] = zn[f];
+                for (int f = 0; f < F; ++f) (rout + f * A.pitch)[j] = zn[f];
             } else {
 #pragma unroll
                 for (int f = 0; f < F; ++f) zn[f] = z[f];

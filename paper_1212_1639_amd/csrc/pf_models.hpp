@@ -23,12 +23,13 @@ __device__ __forceinline__ Words philox(uint64_t seed, uint32_t index, uint32_t 
     uint32_t key_hi = static_cast<uint32_t>(seed >> 32);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0), lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2), lo_b = 0xCD9E8D57u * c2;
-        c0 = hi_b ^ c1 ^ key_lo;
-        c1 = lo_b;
-        c2 = hi_a ^ c3 ^ key_hi;
-        c3 = lo_a;
+        // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32)
+        const uint64_t pa = static_cast<uint64_t>(c0) * 0xD2511F53u;
+        const uint64_t pb = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
+        c0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ key_lo;
+        c1 = static_cast<uint32_t>(pb);
+        c2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ key_hi;
+        c3 = static_cast<uint32_t>(pa);
         key_lo += 0x9E3779B9u;
         key_hi += 0xBB67AE85u;
     }
