@@ -16,6 +16,11 @@ Workloads (all synthetic; data simulated from the model):
               (alpha, beta, sigma^2), N = 2^26, T = 1000, systematic, FP32
   ll_pf_1024  bootstrap filter, local-level model, known variances,
               N = 1024, T = 100, multinomial, FP64
+  ll_pl_batch256  256 independent local-level particle-learning filters, each
+              with its own seed and data, N drawn log-uniform in [2^12, 2^18],
+              T = 200, stratified, FP32; stepped together (one persistent
+              launch per step, replayed from a HIP graph) and, for comparison,
+              one after the other ("plain")
 """
 from __future__ import annotations
 
@@ -32,6 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/sec @1 MI355X (batched vs plain), %HBM peak; p50/p99 step latency"
 
 WORKLOADS = {
     "ll_pl_2p20": dict(model="ll_pl", n=1 << 20, T=500, scheme="stratified", fp32=True,
@@ -49,7 +55,113 @@ WORKLOADS = {
     "ll_pf_1024": dict(model="ll_pf", n=1024, T=100, scheme="multinomial", fp32=False,
                        params=dict(x0_mean=0.0, x0_var=10.0, sigma_v2=1.0, sigma_w2=0.1),
                        bytes_per_particle=2 * 8 + 16),
+    "ll_pl_batch256": dict(model="ll_pl", n=None, T=200, scheme="stratified", fp32=True,
+                           filters=256, params=dict(x0_mean=0.0, x0_var=10.0, a_v=2.0, b_v=1.0,
+                                                    a_w=2.0, b_w=1.0),
+                           bytes_per_particle=2 * 20 + 8),
 }
+
+
+def run_batch(args, w, pf, torch):
+    """Batched vs plain stepping of many filters of uneven N."""
+    from paper_1212_1639_amd import inputs
+    nf = w["filters"]
+    sizes = inputs.batch_sizes(nf, 12, 18, seed=0)
+    K = args.steps or w["T"]
+    W = args.warmup
+    T = max(K, W, 1)
+    y = np.stack([inputs.local_level(T, seed=f)[0] for f in range(nf)], axis=1)  # (T, nf)
+    stream = torch.cuda.Stream()
+
+    def filters():
+        return [pf.Filter(pf.make_config(w["model"], int(n), f, scheme=pf.STRATIFIED,
+                                         precision=pf.FP32, items_per_thread=args.items_per_thread,
+                                         **w["params"]), stream=stream)
+                for f, n in enumerate(sizes)]
+
+    if W > 0:
+        warm = filters()
+        b = pf.Batch(warm)
+        b.step(y[:W])
+        torch.cuda.synchronize()
+        b.close()
+        for f in warm:
+            f.close()
+    fs = filters()
+    b = pf.Batch(fs, ring=min(K, 256))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    b.step(y[:K])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    lls = [f.loglik() for f in fs]
+    b.close()
+    for f in fs:
+        f.close()
+    # plain: the same filters, each stepped alone, one after the other
+    ps = filters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, f in enumerate(ps):
+        f.step(y[:K, k])
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
+    lls_plain = [f.loglik() for f in ps]
+    for f in ps:
+        f.close()
+    total = int(sizes.sum())
+    value = total * K / wall
+    step_s = ev_ms * 1e-3 / K
+    bytes_step = w["bytes_per_particle"] * total
+    achieved = bytes_step / step_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "model": w["model"], "filters": nf,
+                   "total_particles": total, "n_min": int(sizes.min()), "n_max": int(sizes.max()),
+                   "T": w["T"], "scheme": w["scheme"], "form": "batched"},
+        "plain": {"value": total * K / wall_plain, "ms_per_step": wall_plain * 1e3 / K},
+        "batched_over_plain": wall_plain / wall,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step_batch + k_scan_batch", "kernel_avg_us": step_s * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_step},
+        "batched_equals_plain_loglik": bool(np.array_equal(np.array(lls), np.array(lls_plain))),
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on the first filters of the same workload, one after the other
+        import oracle
+        budget, used, steps_done, t_cpu = 15.0, 0.0, 0, 0.0
+        done_particles = 0
+        for f, n in enumerate(sizes):
+            cfg = oracle.make_config(oracle.LL_PL, int(n), f, scheme=oracle.STRATIFIED,
+                                     fp32_words=True, **w["params"])
+            t0 = time.perf_counter()
+            oracle.run(cfg, y[:K, f])
+            t_cpu += time.perf_counter() - t0
+            done_particles += int(n)
+            if t_cpu > budget:
+                break
+        out["cpu_baseline"] = {"value": done_particles * K / t_cpu, "unit": "particle-steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {f + 1} of {nf} filters, all {K} steps each "
+                                         f"(sequential FP64 C oracle)"}
+    print(json.dumps(out), flush=True)
 
 
 def data(w, T):
@@ -114,6 +226,10 @@ def main():
         return
 
     w = WORKLOADS[args.workload]
+    if w.get("filters"):
+        torch.cuda.set_device(0)
+        run_batch(args, w, pf, torch)
+        return
     K = args.steps or w["T"]
     W = args.warmup
     y = data(w, max(K, W, 1))
@@ -156,7 +272,7 @@ def main():
     bytes_launch = w["bytes_per_particle"] * n
     achieved = bytes_launch / kern_s / 1e9
     out = {
-        "metric": "particle-steps/sec @1 MI355X (batched vs plain), %HBM peak; p50/p99 step latency",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,

@@ -179,6 +179,37 @@ int pf_destroy(pf_filter* f);
 /* Text of the calling thread's last error ("" if none). */
 const char* pf_last_error(void);
 
+/* ---------------------------------------------------------- batches  */
+/* Many independent filters stepped together (the cycle of Section 3.2 run
+ * for all of them at once): per observation, one persistent launch works
+ * through the tiles of every filter in the batch and one launch scans each
+ * filter's tiles; the pair is captured once in a HIP graph and replayed per
+ * step, its arguments read from a device ring filled ahead of time.  A
+ * filter's results are the same as when it is stepped alone. */
+typedef struct pf_batch pf_batch;
+
+/* Group n >= 1 distinct filters of one model, precision and
+ * items_per_thread, all using the default tile scan.  The batch launches on
+ * the first filter's stream; the filters keep their own workspaces and must
+ * not be stepped on their own while the batch is used (pf_loglik,
+ * pf_moments and pf_debug_particles on them remain valid).  ring (0 = 64)
+ * is how many steps' arguments one pf_batch_step call can queue at once.
+ * Errors: PF_EINVAL, PF_ENOMEM, PF_EDEVICE. */
+int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t ring, pf_batch** out);
+
+/* Advance every filter by n_steps observations: y[s * n + f] (host memory,
+ * read before return) is filter f's observation at step s.  Asynchronous.
+ * Errors: PF_EINVAL (n_steps < 1, a non-finite observation: nothing is
+ * launched), PF_EDEVICE. */
+int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps);
+
+/* Release a batch (not its filters).  NULL is accepted. */
+int pf_batch_destroy(pf_batch* b);
+
+/* One step of n filters as a batch: the same as pf_batch_create (ring 1),
+ * pf_batch_step(.., y_each, 1) and pf_batch_destroy. */
+int pf_step_batch(pf_filter* const* filters, int32_t n, const double* y_each);
+
 /* ------------------------------------------------------- test surfaces  */
 /* Inverse-CDF search alone (Section 3.2), the exact-parity surface of the
  * resampling step: anc_dev[j] = min{k : cdf_dev[k] >= u_dev[j]}, or n-1 when

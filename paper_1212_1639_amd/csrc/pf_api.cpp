@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <algorithm>
+#include <vector>
 
 #include "pf.h"
 #include "pf_internal.h"
@@ -15,6 +17,9 @@ hipError_t launch_step(int model, bool fp64, int ipt, const StepArgs& a, int gri
                        bool init);
 hipError_t launch_scan_tiles(const double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
                              int32_t* hint, Totals* tot, DevState* st, hipStream_t s);
+hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int32_t* base,
+                        int32_t n_filters, BatchState* bs, int grid, hipStream_t s);
+int batch_grid(int model, bool fp64, int ipt);
 hipError_t launch_moments(int model, const double* partials, int32_t num_tiles, int64_t n,
                           int32_t weighted, uint32_t t, const ModelParams& p, DevState* st,
                           hipStream_t s);
@@ -231,6 +236,9 @@ struct pf_filter {
         a.partials = at<double>(L.partials);
         a.anc_out = (cfg.flags & PF_FLAG_KEEP_ANCESTORS) ? at<int32_t>(L.anc) : nullptr;
         a.scan = L.lookback ? pf::kScanLookback : pf::kScanTiles;
+        a.ts = L.ts;
+        a.ab_out = at<pf::TileAB>(L.ab);
+        a.hint_out = at<int32_t>(L.hint);
         a.ab_in = at<pf::TileAB>(L.ab);
         a.hint_in = at<int32_t>(L.hint);
         a.agg_out = at<double>(L.agg);
@@ -238,9 +246,11 @@ struct pf_filter {
         return a;
     }
 
-    // One cycle launch.  resample: draw ancestors from the latest CDF;
-    // propagate: move with y_prop; weight: score against y_weight.
-    int launch(bool resample, bool propagate, bool weight, double y_prop, double y_weight) {
+    // Arguments of one cycle and the host-side state change it implies.
+    // resample: draw ancestors from the latest CDF; propagate: move with
+    // y_prop; weight: score against y_weight.
+    pf::StepArgs prepare(bool resample, bool propagate, bool weight, double y_prop,
+                         double y_weight) {
         pf::StepArgs a = args();
         a.flags = (resample ? pf::kResample : 0) | (propagate ? pf::kPropagate : 0) |
                   (weight ? pf::kWeight : 0);
@@ -263,15 +273,6 @@ struct pf_filter {
             if (++epoch == 0) epoch = 1;
         }
         a.epoch = epoch;
-        hipError_t e = pf::launch_step(cfg.model, cfg.precision == PF_FP64, L.ipt, a, L.num_tiles,
-                                       stream, false);
-        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
-        if (weight && !L.lookback) {
-            e = pf::launch_scan_tiles(a.agg_out, L.num_tiles, cfg.n_particles, L.ts,
-                                      at<pf::TileAB>(L.ab), at<int32_t>(L.hint), a.tot_out, a.st,
-                                      stream);
-            if (e != hipSuccess) return hip_fail(e, "tile scan launch");
-        }
         if (propagate) {
             cur = 1 - cur;
             ++t;
@@ -283,10 +284,58 @@ struct pf_filter {
             have_cdf = false;
         }
         weighted_partials = weighted_mom ? 1 : 0;
+        return a;
+    }
+
+    // The cycle for one observation: particle learning weights y_{t+1}
+    // before it propagates with y_t, so it runs one observation behind.
+    pf::StepArgs prepare_obs(double y) {
+        if (cfg.model == PF_LL_PL) {
+            pf::StepArgs a = pending ? prepare(true, true, true, y_pend, y)
+                                     : prepare(false, false, true, 0.0, y);
+            pending = true;
+            y_pend = y;
+            return a;
+        }
+        return prepare(have_cdf, true, true, y, y);
+    }
+
+    int run(const pf::StepArgs& a) {
+        hipError_t e = pf::launch_step(cfg.model, cfg.precision == PF_FP64, L.ipt, a, L.num_tiles,
+                                       stream, false);
+        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        if ((a.flags & pf::kWeight) && !L.lookback) {
+            e = pf::launch_scan_tiles(a.agg_out, L.num_tiles, cfg.n_particles, L.ts,
+                                      at<pf::TileAB>(L.ab), at<int32_t>(L.hint), a.tot_out, a.st,
+                                      stream);
+            if (e != hipSuccess) return hip_fail(e, "tile scan launch");
+        }
         return PF_OK;
+    }
+
+    int launch(bool resample, bool propagate, bool weight, double y_prop, double y_weight) {
+        return run(prepare(resample, propagate, weight, y_prop, y_weight));
     }
 };
 
+// A batch: filters of one model, precision and tile size whose cycles run
+// together, one persistent step launch and one scan launch per observation,
+// replayed from a captured graph.  Each step's arguments are staged in a
+// device ring of `ring` blocks of n StepArgs.
+struct pf_batch {
+    std::vector<pf_filter*> fs;
+    hipStream_t stream = nullptr;
+    int model = 0, ipt = 0, grid = 0;
+    bool fp64 = false;
+    int32_t ring = 0;
+    uint64_t issued = 0;          // steps queued so far (the device counter follows)
+    pf::StepArgs* d_descs = nullptr;
+    int32_t* d_base = nullptr;
+    pf::BatchState* d_state = nullptr;
+    pf::StepArgs* h_stage = nullptr;  // pinned staging of the ring
+    hipEvent_t staged = nullptr;      // the latest staging copy has been consumed
+    hipGraphExec_t exec = nullptr;
+};
 extern "C" {
 
 int pf_fields(int32_t model) { return model_fields(model); }
@@ -351,20 +400,7 @@ int pf_step(pf_filter* f, const double* y, int64_t n_obs) {
     for (int64_t i = 0; i < n_obs; ++i)
         if (!std::isfinite(y[i])) return fail(PF_EINVAL, "observation is not finite");
     for (int64_t i = 0; i < n_obs; ++i) {
-        int rc;
-        if (f->cfg.model == PF_LL_PL) {
-            // Step 1 weights the current particles with p(y_{t+1} | z_t), so a
-            // cycle propagates with y_t only once y_{t+1} is known
-            if (!f->pending) {
-                rc = f->launch(false, false, true, 0.0, y[i]);
-            } else {
-                rc = f->launch(true, true, true, f->y_pend, y[i]);
-            }
-            f->pending = true;
-            f->y_pend = y[i];
-        } else {
-            rc = f->launch(f->have_cdf, true, true, y[i], y[i]);
-        }
+        const int rc = f->run(f->prepare_obs(y[i]));
         if (rc != PF_OK) return rc;
     }
     return PF_OK;
@@ -470,6 +506,148 @@ int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_ou
     if (e != hipSuccess) return hip_fail(e, "pf_debug_particles");
     if (t_out) *t_out = f->t;
     return PF_OK;
+}
+
+int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t ring, pf_batch** out) {
+    if (!out) return fail(PF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!filters || n < 1) return fail(PF_EINVAL, "need at least one filter");
+    if (ring < 1) ring = 64;
+    const pf_filter* f0 = filters[0];
+    if (!f0) return fail(PF_EINVAL, "filter is NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        const pf_filter* f = filters[i];
+        if (!f) return fail(PF_EINVAL, "filter is NULL");
+        if (f->cfg.model != f0->cfg.model || f->cfg.precision != f0->cfg.precision ||
+            f->L.ipt != f0->L.ipt)
+            return fail(PF_EINVAL, "a batch needs one model, precision and items_per_thread");
+        if (f->L.lookback) return fail(PF_EINVAL, "batched filters use the tile scan");
+        for (int32_t k = 0; k < i; ++k)
+            if (filters[k] == f) return fail(PF_EINVAL, "a filter appears twice in the batch");
+    }
+    // work already queued on the filters' own streams finishes first
+    for (int32_t i = 0; i < n; ++i) {
+        const hipError_t se = hipStreamSynchronize(filters[i]->stream);
+        if (se != hipSuccess) return hip_fail(se, "pf_batch_create synchronise");
+    }
+    pf_batch* b = new (std::nothrow) pf_batch();
+    if (!b) return fail(PF_ENOMEM, "host allocation failed");
+    b->fs.assign(filters, filters + n);
+    b->stream = f0->stream;
+    b->model = f0->cfg.model;
+    b->fp64 = f0->cfg.precision == PF_FP64;
+    b->ipt = f0->L.ipt;
+    b->ring = ring;
+    std::vector<int32_t> base(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        if (static_cast<int64_t>(base[i]) + filters[i]->L.num_tiles > INT32_MAX) {
+            delete b;
+            return fail(PF_EINVAL, "too many tiles in one batch");
+        }
+        base[i + 1] = base[i] + filters[i]->L.num_tiles;
+    }
+    const size_t ring_bytes = sizeof(pf::StepArgs) * static_cast<size_t>(ring) * n;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_descs), ring_bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_base), sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_state), sizeof(pf::BatchState));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_stage), ring_bytes, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    pf::BatchState bs{};
+    bs.ring = static_cast<uint32_t>(ring);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_base, base.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_state, &bs, sizeof(bs), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        pf_batch_destroy(b);
+        return hip_fail(e, "pf_batch_create");
+    }
+    b->grid = pf::batch_grid(b->model, b->fp64, b->ipt);
+    if (b->grid > base[n]) b->grid = base[n];
+    if (b->grid < 1) b->grid = 1;
+    *out = b;
+    return PF_OK;
+}
+
+int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
+    if (!b) return fail(PF_EINVAL, "batch is NULL");
+    if (!y || n_steps < 1) return fail(PF_EINVAL, "need n_steps >= 1 observations per filter");
+    const int64_t n = static_cast<int64_t>(b->fs.size());
+    for (int64_t i = 0; i < n * n_steps; ++i)
+        if (!std::isfinite(y[i])) return fail(PF_EINVAL, "observation is not finite");
+    hipError_t e = hipSuccess;
+    if (!b->exec) {
+        // capture one batched cycle (its arguments come from the device ring)
+        // on a private stream: the filters' stream may be the null stream,
+        // which cannot capture; the graph is then launched on that stream
+        hipGraph_t g = nullptr;
+        hipStream_t cap = nullptr;
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = pf::launch_batch(b->model, b->fp64, b->ipt, b->d_descs, b->d_base,
+                                             static_cast<int32_t>(n), b->d_state, b->grid, cap);
+            e = hipStreamEndCapture(cap, &g);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+        if (cap) hipStreamDestroy(cap);
+        if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+    }
+    int64_t done = 0;
+    while (done < n_steps) {
+        // stage up to `ring` steps at once (the previous staging copy must
+        // have been consumed before the pinned buffer is rewritten)
+        const int64_t chunk = std::min<int64_t>(b->ring, n_steps - done);
+        e = hipEventSynchronize(b->staged);
+        if (e != hipSuccess) return hip_fail(e, "batch staging wait");
+        const uint64_t first = b->issued;
+        for (int64_t s = 0; s < chunk; ++s) {
+            const uint64_t slot = (first + s) % static_cast<uint64_t>(b->ring);
+            for (int64_t i = 0; i < n; ++i)
+                b->h_stage[slot * n + i] = b->fs[i]->prepare_obs(y[(done + s) * n + i]);
+        }
+        // the slots [first, first+chunk) mod ring, in at most two pieces
+        const uint64_t s0 = first % static_cast<uint64_t>(b->ring);
+        const uint64_t c0 = std::min<uint64_t>(chunk, b->ring - s0);
+        e = hipMemcpyAsync(b->d_descs + s0 * n, b->h_stage + s0 * n, sizeof(pf::StepArgs) * c0 * n,
+                           hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess && c0 < static_cast<uint64_t>(chunk))
+            e = hipMemcpyAsync(b->d_descs, b->h_stage, sizeof(pf::StepArgs) * (chunk - c0) * n,
+                               hipMemcpyHostToDevice, b->stream);
+        for (int64_t s = 0; s < chunk && e == hipSuccess; ++s) e = hipGraphLaunch(b->exec, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(b->staged, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch step");
+        b->issued += chunk;
+        done += chunk;
+    }
+    return PF_OK;
+}
+
+int pf_batch_destroy(pf_batch* b) {
+    if (!b) return PF_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->staged) hipEventDestroy(b->staged);
+    if (b->h_stage) hipHostFree(b->h_stage);
+    if (b->d_descs) hipFree(b->d_descs);
+    if (b->d_base) hipFree(b->d_base);
+    if (b->d_state) hipFree(b->d_state);
+    delete b;
+    if (e != hipSuccess) return hip_fail(e, "pf_batch_destroy synchronise");
+    return PF_OK;
+}
+
+int pf_step_batch(pf_filter* const* filters, int32_t n, const double* y_each) {
+    pf_batch* b = nullptr;
+    int rc = pf_batch_create(filters, n, 1, &b);
+    if (rc != PF_OK) return rc;
+    rc = pf_batch_step(b, y_each, 1);
+    const int rc2 = pf_batch_destroy(b);
+    return rc != PF_OK ? rc : rc2;
 }
 
 }  // extern "C"

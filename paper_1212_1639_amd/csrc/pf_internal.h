@@ -92,7 +92,7 @@ struct StepArgs {
     int32_t strategy;
     int32_t flags;       // StepFlags
     int32_t scan;        // Scan
-    int32_t pad0;
+    int32_t ts;          // particles per tile
     uint32_t t;          // time index of this step's draws (1-based)
     uint32_t epoch;      // tag of this launch's look-back words (never 0)
     uint64_t seed;
@@ -111,11 +111,22 @@ struct StepArgs {
     TileInfo* tiles_out;
     Totals* tot_out;
     double* agg_out;            // tile-scan: this step's (m_b, s_b) per tile
+    TileAB* ab_out;             // tile-scan outputs (the arrays ab_in / hint_in
+    int32_t* hint_out;          //   point to, read by the next step)
     uint64_t* status;
     DevState* st;
     double* partials;
     int32_t* anc_out;    // ancestors of this step (NULL: not kept)
     ModelParams p;
+};
+
+// Device-side progress of a batch of filters stepped together.
+struct BatchState {
+    uint64_t step;    // steps completed; selects the argument block of the next step
+    uint64_t ticket;  // global tile ticket of the running step
+    uint32_t done;    // scan work-groups finished in the running step
+    uint32_t ring;    // argument blocks in the ring (steps that can be queued)
+    uint64_t pad[5];
 };
 
 }  // namespace pf

@@ -321,35 +321,23 @@ struct StepSmem {
     double ex_m, ex_s;
 };
 
-// ------------------------------------------------------------ the cycle kernel
+// ------------------------------------------------------------ the cycle
+// One tile of one filter's cycle (the work of one work-group).
 template <int MODEL, typename R, int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
+__device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
+                                      StepSmem<BLOCK, IPT>& sm) {
     using MD = ModelDef<MODEL>;
     constexpr int F = MD::F, NG = MD::NG;
     constexpr int TS = BLOCK * IPT, NW = BLOCK / kWave;
     constexpr int WIN = StepSmem<BLOCK, IPT>::WIN;
-    __shared__ StepSmem<BLOCK, IPT> sm;
 
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const bool weight = (A.flags & kWeight) != 0;
     const bool resample = (A.flags & kResample) != 0;
     const bool propagate = (A.flags & kPropagate) != 0;
     const bool weighted_mom = (A.flags & kWeightedMoments) != 0;
-    const int64_t n = A.n;
-
-    // Tile order: with the look-back, a dynamic ticket, so that every tile a
-    // look-back waits on was handed out earlier and is resident or done.
     const bool lookback = weight && A.scan == kScanLookback;
-    uint32_t tile;
-    if (lookback) {
-        if (tid == 0)
-            sm.tile = __hip_atomic_fetch_add(&A.st->ticket, 1u, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        tile = sm.tile;
-    } else {
-        tile = blockIdx.x;
-    }
+    const int64_t n = A.n;
     const int64_t j0 = static_cast<int64_t>(tile) * TS;
 
     // ---------------------------------------------------------- 1. ancestors
@@ -721,6 +709,57 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     }
 }
 
+// One filter, one cycle: a work-group per tile.  With the look-back, tiles
+// are taken from a dynamic ticket, so that every tile a look-back waits on
+// was handed out earlier and is resident or done.
+template <int MODEL, typename R, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
+    __shared__ StepSmem<BLOCK, IPT> sm;
+    uint32_t tile = blockIdx.x;
+    if ((A.flags & kWeight) && A.scan == kScanLookback) {
+        if (threadIdx.x == 0)
+            sm.tile = __hip_atomic_fetch_add(&A.st->ticket, 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        tile = sm.tile;
+    }
+    cycle<MODEL, R, BLOCK, IPT>(A, tile, sm);
+}
+
+// Many filters, one cycle each, in one persistent launch: resident
+// work-groups take global tile numbers from a ticket until all tiles of all
+// filters are done.  Filter f owns global tiles [base[f], base[f+1]); its
+// arguments for step s are descs[(s mod ring) * n_filters + f], where s is
+// the batch's device-side step counter (advanced, and the ticket reset, by
+// k_scan_batch), so the same pair of launches can be replayed step after
+// step.
+template <int MODEL, typename R, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_step_batch(const StepArgs* __restrict__ descs,
+                                                      const int32_t* __restrict__ base,
+                                                      int32_t n_filters, BatchState* bs) {
+    __shared__ StepSmem<BLOCK, IPT> sm;
+    const uint64_t step = __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t total = base[n_filters];
+    const StepArgs* d = descs + (step % static_cast<uint64_t>(bs->ring)) * n_filters;
+    while (true) {
+        if (threadIdx.x == 0)
+            sm.lo = static_cast<int64_t>(__hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT));
+        __syncthreads();
+        const int64_t g = sm.lo;
+        __syncthreads();
+        if (g >= total) break;
+        // owner of global tile g: largest f with base[f] <= g
+        int lo = 0, hi = n_filters - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (base[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        cycle<MODEL, R, BLOCK, IPT>(d[lo], static_cast<uint32_t>(g - base[lo]), sm);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ tile scan
 // One work-group of 1024 threads turns the tiles' (m_b, s_b) into
 //   A_b = sum_{b' < b} s_b' e^{m_b' - M} / S  (non-decreasing),
@@ -732,10 +771,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
 // cycle's tile h starts its search for sorted uniforms.
 constexpr int kScanBlock = 1024;
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const double* agg, int32_t num_tiles,
-                                                           int64_t n, int32_t ts, TileAB* ab,
-                                                           int32_t* hint, Totals* tot,
-                                                           DevState* st) {
+__device__ __forceinline__ void scan_tiles(const double* agg, int32_t num_tiles, int64_t n,
+                                           int32_t ts, TileAB* ab, int32_t* hint, Totals* tot,
+                                           DevState* st) {
     constexpr int NW = kScanBlock / kWave;
     __shared__ double s_m[NW], s_s[NW], s_top[NW];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -813,6 +851,36 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const double* agg, in
         tot->S = S;
         if (!ok) atomicOr(&st->flags, kDegenerate);
         st->loglik += M + log(S / static_cast<double>(n));
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const double* agg, int32_t num_tiles,
+                                                           int64_t n, int32_t ts, TileAB* ab,
+                                                           int32_t* hint, Totals* tot,
+                                                           DevState* st) {
+    scan_tiles(agg, num_tiles, n, ts, ab, hint, tot, st);
+}
+
+// The batch's scans: work-group f scans filter f (if it weighted this step);
+// the last work-group to finish advances the batch's step counter and resets
+// its tile ticket.
+__global__ __launch_bounds__(kScanBlock) void k_scan_batch(const StepArgs* __restrict__ descs,
+                                                           int32_t n_filters, BatchState* bs) {
+    __shared__ uint32_t s_last;
+    const uint64_t step = __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const StepArgs& A = descs[(step % static_cast<uint64_t>(bs->ring)) * n_filters + blockIdx.x];
+    if (A.flags & kWeight)
+        scan_tiles(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out, A.tot_out, A.st);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t d = __hip_atomic_fetch_add(&bs->done, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (d == static_cast<uint32_t>(n_filters - 1)) ? 1u : 0u;
+        if (s_last) {
+            __hip_atomic_store(&bs->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bs->ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bs->step, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -1091,6 +1159,71 @@ hipError_t launch_step(int model, bool fp64, int ipt, const StepArgs& a, int gri
                             : launch_step_m<kSVPL, float>(a, ipt, grid, s, init);
     }
     return hipErrorInvalidValue;
+}
+
+template <int MODEL, typename R, int IPT>
+static hipError_t launch_batch_t(const StepArgs* descs, const int32_t* base, int32_t n_filters,
+                                 BatchState* bs, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_step_batch<MODEL, R, 256, IPT>), dim3(grid), dim3(256), 0, s, descs, base,
+                       n_filters, bs);
+    return hipGetLastError();
+}
+
+template <int MODEL, typename R>
+static hipError_t launch_batch_m(int ipt, const StepArgs* descs, const int32_t* base,
+                                 int32_t n_filters, BatchState* bs, int grid, hipStream_t s) {
+    switch (ipt) {
+    case 1: return launch_batch_t<MODEL, R, 1>(descs, base, n_filters, bs, grid, s);
+    case 2: return launch_batch_t<MODEL, R, 2>(descs, base, n_filters, bs, grid, s);
+    case 4: return launch_batch_t<MODEL, R, 4>(descs, base, n_filters, bs, grid, s);
+    case 8: return launch_batch_t<MODEL, R, 8>(descs, base, n_filters, bs, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// One batched cycle: the persistent step kernel over all filters' tiles,
+// then one scan work-group per filter.
+hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int32_t* base,
+                        int32_t n_filters, BatchState* bs, int grid, hipStream_t s) {
+    hipError_t e = hipErrorInvalidValue;
+    switch (model) {
+    case kLLPF: e = fp64 ? launch_batch_m<kLLPF, double>(ipt, descs, base, n_filters, bs, grid, s)
+                         : launch_batch_m<kLLPF, float>(ipt, descs, base, n_filters, bs, grid, s); break;
+    case kLLPL: e = fp64 ? launch_batch_m<kLLPL, double>(ipt, descs, base, n_filters, bs, grid, s)
+                         : launch_batch_m<kLLPL, float>(ipt, descs, base, n_filters, bs, grid, s); break;
+    case kSVPF: e = fp64 ? launch_batch_m<kSVPF, double>(ipt, descs, base, n_filters, bs, grid, s)
+                         : launch_batch_m<kSVPF, float>(ipt, descs, base, n_filters, bs, grid, s); break;
+    case kSVPL: e = fp64 ? launch_batch_m<kSVPL, double>(ipt, descs, base, n_filters, bs, grid, s)
+                         : launch_batch_m<kSVPL, float>(ipt, descs, base, n_filters, bs, grid, s); break;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_batch, dim3(n_filters), dim3(kScanBlock), 0, s, descs, n_filters, bs);
+    return hipGetLastError();
+}
+
+// Resident work-groups of the persistent batch kernel on this device.
+int batch_grid(int model, bool fp64, int ipt) {
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) == hipSuccess)
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void* fn = nullptr;
+#define PF_FN(M, RR, I) reinterpret_cast<const void*>(&k_step_batch<M, RR, 256, I>)
+#define PF_SEL(M)                                                                               \
+    fn = fp64 ? (ipt == 1 ? PF_FN(M, double, 1) : ipt == 2 ? PF_FN(M, double, 2)               \
+                 : ipt == 4 ? PF_FN(M, double, 4) : PF_FN(M, double, 8))                       \
+              : (ipt == 1 ? PF_FN(M, float, 1) : ipt == 2 ? PF_FN(M, float, 2)                  \
+                 : ipt == 4 ? PF_FN(M, float, 4) : PF_FN(M, float, 8))
+    switch (model) {
+    case kLLPF: PF_SEL(kLLPF); break;
+    case kLLPL: PF_SEL(kLLPL); break;
+    case kSVPF: PF_SEL(kSVPF); break;
+    case kSVPL: PF_SEL(kSVPL); break;
+    }
+#undef PF_SEL
+#undef PF_FN
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1)
+        per = 1;
+    return cus * per;
 }
 
 hipError_t launch_scan_tiles(const double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
