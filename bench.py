@@ -16,6 +16,12 @@ Workloads (all synthetic; data simulated from the model):
               (alpha, beta, sigma^2), N = 2^26, T = 1000, systematic, FP32
   ll_pf_1024  bootstrap filter, local-level model, known variances,
               N = 1024, T = 100, multinomial, FP64
+  served_mix  a Poisson stream (200 requests/s for 30 s) of filter requests,
+              half local-level, half stochastic-volatility particle learning,
+              N log-uniform in [2^10, 2^20], T uniform in [50, 1000], served
+              with continuous batching under a memory budget (80% of free
+              device memory, or --serve-budget-gb); reports p50/p99 per-step
+              latency and aggregate particle-steps/s
   ll_pl_batch256  256 independent local-level particle-learning filters, each
               with its own seed and data, N drawn log-uniform in [2^12, 2^18],
               T = 200, stratified, FP32; stepped together (one persistent
@@ -55,11 +61,53 @@ WORKLOADS = {
     "ll_pf_1024": dict(model="ll_pf", n=1024, T=100, scheme="multinomial", fp32=False,
                        params=dict(x0_mean=0.0, x0_var=10.0, sigma_v2=1.0, sigma_w2=0.1),
                        bytes_per_particle=2 * 8 + 16),
+    "served_mix": dict(model="mix", n=None, T=None, scheme="mixed", fp32=True, served=True,
+                       rate=200.0, duration=30.0, bytes_per_particle=None),
     "ll_pl_batch256": dict(model="ll_pl", n=None, T=200, scheme="stratified", fp32=True,
                            filters=256, params=dict(x0_mean=0.0, x0_var=10.0, a_v=2.0, b_v=1.0,
                                                     a_w=2.0, b_w=1.0),
                            bytes_per_particle=2 * 20 + 8),
 }
+
+
+def run_served(args, w, pf, torch):
+    """The served workload: continuous batching of a Poisson request stream."""
+    from paper_1212_1639_amd import inputs
+    from paper_1212_1639_amd.serve import GpuBackend, Server, stream_requests
+    duration = args.serve_seconds or w["duration"]
+    specs = inputs.poisson_requests(rate=w["rate"], duration=duration, seed=0)
+    reqs = stream_requests(specs, lambda T, s: inputs.local_level(T, seed=s)[0],
+                           lambda T, s: inputs.stochastic_volatility(T, seed=s)[0])
+    groups = {"ll": dict(model="ll_pl", scheme=pf.STRATIFIED,
+                         params=WORKLOADS["ll_pl_2p20"]["params"]),
+              "sv": dict(model="sv_pl", scheme=pf.SYSTEMATIC,
+                         params=WORKLOADS["sv_pl_2p26"]["params"])}
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(args.serve_budget_gb * 2**30) if args.serve_budget_gb else int(0.8 * free)
+    be = GpuBackend(groups, capacity=1024)
+    srv = Server(be, budget_bytes=budget)
+    st = srv.run(reqs, realtime=True)
+    be.close()
+    out = {
+        "metric": METRIC,
+        "value": st["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": st["ticks"],
+        "warmup": 0,
+        "ms_per_step": st["wall_s"] * 1e3 / max(1, st["ticks"]),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "rate_per_s": w["rate"], "duration_s": duration,
+                   "requests": st["requests"], "budget_bytes": budget, "form": "served"},
+        "served": {k: st[k] for k in ("completed", "rejected", "ticks", "wall_s",
+                                      "particle_steps", "step_latency_ms", "queue_delay_ms",
+                                      "max_bytes_in_use")},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_batch(args, w, pf, torch):
@@ -202,6 +250,10 @@ def main():
     ap.add_argument("--workload", default="ll_pl_2p20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--items-per-thread", type=int, default=0)
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="served_mix: device memory budget (default 80%% of free memory)")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="served_mix: length of the arrival window (default 30 s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the filter, copy MIB mebibytes device to device (a plain "
                          "copy kernel of known size, to scale the profiler's byte counters)")
@@ -226,6 +278,10 @@ def main():
         return
 
     w = WORKLOADS[args.workload]
+    if w.get("served"):
+        torch.cuda.set_device(0)
+        run_served(args, w, pf, torch)
+        return
     if w.get("filters"):
         torch.cuda.set_device(0)
         run_batch(args, w, pf, torch)

@@ -189,16 +189,25 @@ const char* pf_last_error(void);
 typedef struct pf_batch pf_batch;
 
 /* Group n >= 1 distinct filters of one model, precision and
- * items_per_thread, all using the default tile scan.  The batch launches on
- * the first filter's stream; the filters keep their own workspaces and must
- * not be stepped on their own while the batch is used (pf_loglik,
- * pf_moments and pf_debug_particles on them remain valid).  ring (0 = 64)
- * is how many steps' arguments one pf_batch_step call can queue at once.
- * Errors: PF_EINVAL, PF_ENOMEM, PF_EDEVICE. */
-int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t ring, pf_batch** out);
+ * items_per_thread, all using the default tile scan.  capacity (>= n; less
+ * means n) bounds the membership pf_batch_update may set later.  The batch
+ * launches on the first filter's stream; the filters keep their own
+ * workspaces and must not be stepped on their own while they are members
+ * (pf_loglik, pf_moments and pf_debug_particles on them remain valid).  ring
+ * (0 = 64) is how many steps' arguments one pf_batch_step call can queue at
+ * once.  Errors: PF_EINVAL, PF_ENOMEM, PF_EDEVICE. */
+int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t capacity, int32_t ring,
+                    pf_batch** out);
 
-/* Advance every filter by n_steps observations: y[s * n + f] (host memory,
- * read before return) is filter f's observation at step s.  Asynchronous.
+/* Replace the members (0 <= n <= capacity; same model, precision and
+ * items_per_thread as at creation).  Filters may join at any stage and leave
+ * at any time; the batch's captured graph stays valid.  Ordered on the
+ * batch's stream.  Errors: PF_EINVAL, PF_EDEVICE. */
+int pf_batch_update(pf_batch* b, pf_filter* const* filters, int32_t n);
+
+/* Advance every member by n_steps observations: y[s * n + f] (host memory,
+ * read before return) is member f's observation at step s (n = current
+ * members; nothing happens when there are none).  Asynchronous.
  * Errors: PF_EINVAL (n_steps < 1, a non-finite observation: nothing is
  * launched), PF_EDEVICE. */
 int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps);
@@ -206,8 +215,8 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps);
 /* Release a batch (not its filters).  NULL is accepted. */
 int pf_batch_destroy(pf_batch* b);
 
-/* One step of n filters as a batch: the same as pf_batch_create (ring 1),
- * pf_batch_step(.., y_each, 1) and pf_batch_destroy. */
+/* One step of n filters as a batch: the same as pf_batch_create (capacity
+ * n, ring 1), pf_batch_step(.., y_each, 1) and pf_batch_destroy. */
 int pf_step_batch(pf_filter* const* filters, int32_t n, const double* y_each);
 
 /* ------------------------------------------------------- test surfaces  */

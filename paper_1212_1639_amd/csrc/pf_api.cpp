@@ -327,13 +327,20 @@ struct pf_batch {
     hipStream_t stream = nullptr;
     int model = 0, ipt = 0, grid = 0;
     bool fp64 = false;
-    int32_t ring = 0;
+    int32_t ring = 0, capacity = 0;
+    int64_t total_tiles = 0;
     uint64_t issued = 0;          // steps queued so far (the device counter follows)
     pf::StepArgs* d_descs = nullptr;
     int32_t* d_base = nullptr;
     pf::BatchState* d_state = nullptr;
     pf::StepArgs* h_stage = nullptr;  // pinned staging of the ring
-    hipEvent_t staged = nullptr;      // the latest staging copy has been consumed
+    std::vector<hipEvent_t> slot_copied;  // slot's staging copy has completed
+    // pinned staging of membership updates: kMemberSlots blocks of
+    // (capacity + 1) tile offsets followed by the member count
+    static constexpr int kMemberSlots = 4;
+    int32_t* h_member = nullptr;
+    hipEvent_t member_copied[kMemberSlots] = {};
+    int member_next = 0;
     hipGraphExec_t exec = nullptr;
 };
 extern "C" {
@@ -508,65 +515,111 @@ int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_ou
     return PF_OK;
 }
 
-int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t ring, pf_batch** out) {
+namespace {
+// A filter may join a batch of this model, precision and tile size.
+int check_member(const pf_filter* f, int model, int precision, int ipt) {
+    if (!f) return fail(PF_EINVAL, "filter is NULL");
+    if (f->cfg.model != model || f->cfg.precision != precision || f->L.ipt != ipt)
+        return fail(PF_EINVAL, "a batch needs one model, precision and items_per_thread");
+    if (f->L.lookback) return fail(PF_EINVAL, "batched filters use the tile scan");
+    return PF_OK;
+}
+}  // namespace
+
+int pf_batch_update(pf_batch* b, pf_filter* const* filters, int32_t n) {
+    if (!b) return fail(PF_EINVAL, "batch is NULL");
+    if (n < 0 || n > b->capacity || (n > 0 && !filters))
+        return fail(PF_EINVAL, "need 0 <= n <= the batch's capacity filters");
+    const int precision = b->fp64 ? PF_FP64 : PF_FP32;
+    for (int32_t i = 0; i < n; ++i) {
+        const int rc = check_member(filters[i], b->model, precision, b->ipt);
+        if (rc != PF_OK) return rc;
+        for (int32_t k = 0; k < i; ++k)
+            if (filters[k] == filters[i]) return fail(PF_EINVAL, "a filter appears twice in the batch");
+    }
+    // work already queued on the members' own streams finishes first
+    for (int32_t i = 0; i < n; ++i) {
+        if (filters[i]->stream == b->stream) continue;
+        const hipError_t se = hipStreamSynchronize(filters[i]->stream);
+        if (se != hipSuccess) return hip_fail(se, "pf_batch_update synchronise");
+    }
+    std::vector<int32_t> base(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        if (static_cast<int64_t>(base[i]) + filters[i]->L.num_tiles > INT32_MAX)
+            return fail(PF_EINVAL, "too many tiles in one batch");
+        base[i + 1] = base[i] + filters[i]->L.num_tiles;
+    }
+    // a pinned block whose previous copy has completed (kMemberSlots updates ago)
+    const int k = b->member_next;
+    b->member_next = (k + 1) % pf_batch::kMemberSlots;
+    hipError_t e = hipEventSynchronize(b->member_copied[k]);
+    if (e != hipSuccess) return hip_fail(e, "pf_batch_update wait");
+    int32_t* blk = b->h_member + static_cast<size_t>(k) * (b->capacity + 2);
+    std::memcpy(blk, base.data(), sizeof(int32_t) * (n + 1));
+    blk[b->capacity + 1] = n;
+    e = hipMemcpyAsync(b->d_base, blk, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&b->d_state->n_filters, blk + b->capacity + 1, sizeof(int32_t),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->member_copied[k], b->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_batch_update copy");
+    b->fs.assign(filters, filters + n);
+    b->total_tiles = base[n];
+    return PF_OK;
+}
+
+int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t capacity, int32_t ring,
+                    pf_batch** out) {
     if (!out) return fail(PF_EINVAL, "out is NULL");
     *out = nullptr;
     if (!filters || n < 1) return fail(PF_EINVAL, "need at least one filter");
+    if (capacity < n) capacity = n;
     if (ring < 1) ring = 64;
     const pf_filter* f0 = filters[0];
-    if (!f0) return fail(PF_EINVAL, "filter is NULL");
-    for (int32_t i = 0; i < n; ++i) {
-        const pf_filter* f = filters[i];
-        if (!f) return fail(PF_EINVAL, "filter is NULL");
-        if (f->cfg.model != f0->cfg.model || f->cfg.precision != f0->cfg.precision ||
-            f->L.ipt != f0->L.ipt)
-            return fail(PF_EINVAL, "a batch needs one model, precision and items_per_thread");
-        if (f->L.lookback) return fail(PF_EINVAL, "batched filters use the tile scan");
-        for (int32_t k = 0; k < i; ++k)
-            if (filters[k] == f) return fail(PF_EINVAL, "a filter appears twice in the batch");
-    }
-    // work already queued on the filters' own streams finishes first
-    for (int32_t i = 0; i < n; ++i) {
-        const hipError_t se = hipStreamSynchronize(filters[i]->stream);
-        if (se != hipSuccess) return hip_fail(se, "pf_batch_create synchronise");
-    }
+    int rc = check_member(f0, f0 ? f0->cfg.model : 0, f0 ? f0->cfg.precision : 0,
+                          f0 ? f0->L.ipt : 0);
+    if (rc != PF_OK) return rc;
     pf_batch* b = new (std::nothrow) pf_batch();
     if (!b) return fail(PF_ENOMEM, "host allocation failed");
-    b->fs.assign(filters, filters + n);
     b->stream = f0->stream;
     b->model = f0->cfg.model;
     b->fp64 = f0->cfg.precision == PF_FP64;
     b->ipt = f0->L.ipt;
     b->ring = ring;
-    std::vector<int32_t> base(n + 1, 0);
-    for (int32_t i = 0; i < n; ++i) {
-        if (static_cast<int64_t>(base[i]) + filters[i]->L.num_tiles > INT32_MAX) {
-            delete b;
-            return fail(PF_EINVAL, "too many tiles in one batch");
-        }
-        base[i + 1] = base[i] + filters[i]->L.num_tiles;
-    }
-    const size_t ring_bytes = sizeof(pf::StepArgs) * static_cast<size_t>(ring) * n;
+    b->capacity = capacity;
+    const size_t ring_bytes = sizeof(pf::StepArgs) * static_cast<size_t>(ring) * capacity;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_descs), ring_bytes);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_base), sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void**>(&b->d_base), sizeof(int32_t) * (capacity + 1));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_state), sizeof(pf::BatchState));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_stage), ring_bytes, 0);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
-    pf::BatchState bs{};
-    bs.ring = static_cast<uint32_t>(ring);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_base, base.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice,
-                           b->stream);
-    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_member),
+                          sizeof(int32_t) * pf_batch::kMemberSlots * (capacity + 2), 0);
+    b->slot_copied.assign(ring, nullptr);
+    for (int32_t i = 0; i < ring && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&b->slot_copied[i], hipEventDisableTiming);
+    for (int i = 0; i < pf_batch::kMemberSlots && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&b->member_copied[i], hipEventDisableTiming);
+    if (e == hipSuccess) {
+        pf::BatchState bs{};
+        bs.ring = static_cast<uint32_t>(ring);
+        bs.capacity = capacity;
+        // pageable source; the synchronisation below completes the copy
         e = hipMemcpyAsync(b->d_state, &bs, sizeof(bs), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         pf_batch_destroy(b);
         return hip_fail(e, "pf_batch_create");
     }
     b->grid = pf::batch_grid(b->model, b->fp64, b->ipt);
-    if (b->grid > base[n]) b->grid = base[n];
-    if (b->grid < 1) b->grid = 1;
+    rc = pf_batch_update(b, filters, n);
+    if (rc != PF_OK) {
+        pf_batch_destroy(b);
+        return rc;
+    }
     *out = b;
     return PF_OK;
 }
@@ -575,6 +628,8 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
     if (!b) return fail(PF_EINVAL, "batch is NULL");
     if (!y || n_steps < 1) return fail(PF_EINVAL, "need n_steps >= 1 observations per filter");
     const int64_t n = static_cast<int64_t>(b->fs.size());
+    if (n == 0) return PF_OK;  // an empty batch has nothing to step
+    const int64_t cap = b->capacity;
     for (int64_t i = 0; i < n * n_steps; ++i)
         if (!std::isfinite(y[i])) return fail(PF_EINVAL, "observation is not finite");
     hipError_t e = hipSuccess;
@@ -583,18 +638,18 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
         // on a private stream: the filters' stream may be the null stream,
         // which cannot capture; the graph is then launched on that stream
         hipGraph_t g = nullptr;
-        hipStream_t cap = nullptr;
-        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        hipStream_t cs = nullptr;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             hipError_t le = pf::launch_batch(b->model, b->fp64, b->ipt, b->d_descs, b->d_base,
-                                             static_cast<int32_t>(n), b->d_state, b->grid, cap);
-            e = hipStreamEndCapture(cap, &g);
+                                             b->capacity, b->d_state, b->grid, cs);
+            e = hipStreamEndCapture(cs, &g);
             if (le != hipSuccess) e = le;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
         if (g) hipGraphDestroy(g);
-        if (cap) hipStreamDestroy(cap);
+        if (cs) hipStreamDestroy(cs);
         if (e != hipSuccess) return hip_fail(e, "batch graph capture");
     }
     int64_t done = 0;
@@ -602,24 +657,27 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
         // stage up to `ring` steps at once (the previous staging copy must
         // have been consumed before the pinned buffer is rewritten)
         const int64_t chunk = std::min<int64_t>(b->ring, n_steps - done);
-        e = hipEventSynchronize(b->staged);
-        if (e != hipSuccess) return hip_fail(e, "batch staging wait");
         const uint64_t first = b->issued;
         for (int64_t s = 0; s < chunk; ++s) {
             const uint64_t slot = (first + s) % static_cast<uint64_t>(b->ring);
+            // the copy that last read this pinned slot (ring steps ago) is done
+            e = hipEventSynchronize(b->slot_copied[slot]);
+            if (e != hipSuccess) return hip_fail(e, "batch staging wait");
             for (int64_t i = 0; i < n; ++i)
-                b->h_stage[slot * n + i] = b->fs[i]->prepare_obs(y[(done + s) * n + i]);
+                b->h_stage[slot * cap + i] = b->fs[i]->prepare_obs(y[(done + s) * n + i]);
         }
         // the slots [first, first+chunk) mod ring, in at most two pieces
         const uint64_t s0 = first % static_cast<uint64_t>(b->ring);
         const uint64_t c0 = std::min<uint64_t>(chunk, b->ring - s0);
-        e = hipMemcpyAsync(b->d_descs + s0 * n, b->h_stage + s0 * n, sizeof(pf::StepArgs) * c0 * n,
-                           hipMemcpyHostToDevice, b->stream);
+        e = hipMemcpyAsync(b->d_descs + s0 * cap, b->h_stage + s0 * cap,
+                           sizeof(pf::StepArgs) * c0 * cap, hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess && c0 < static_cast<uint64_t>(chunk))
-            e = hipMemcpyAsync(b->d_descs, b->h_stage, sizeof(pf::StepArgs) * (chunk - c0) * n,
+            e = hipMemcpyAsync(b->d_descs, b->h_stage, sizeof(pf::StepArgs) * (chunk - c0) * cap,
                                hipMemcpyHostToDevice, b->stream);
+        for (int64_t s = 0; s < chunk && e == hipSuccess; ++s)
+            e = hipEventRecord(b->slot_copied[(first + s) % static_cast<uint64_t>(b->ring)],
+                               b->stream);
         for (int64_t s = 0; s < chunk && e == hipSuccess; ++s) e = hipGraphLaunch(b->exec, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(b->staged, b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch step");
         b->issued += chunk;
         done += chunk;
@@ -631,8 +689,12 @@ int pf_batch_destroy(pf_batch* b) {
     if (!b) return PF_OK;
     hipError_t e = hipStreamSynchronize(b->stream);
     if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->staged) hipEventDestroy(b->staged);
+    for (hipEvent_t ev : b->slot_copied)
+        if (ev) hipEventDestroy(ev);
+    for (hipEvent_t ev : b->member_copied)
+        if (ev) hipEventDestroy(ev);
     if (b->h_stage) hipHostFree(b->h_stage);
+    if (b->h_member) hipHostFree(b->h_member);
     if (b->d_descs) hipFree(b->d_descs);
     if (b->d_base) hipFree(b->d_base);
     if (b->d_state) hipFree(b->d_state);
@@ -643,7 +705,7 @@ int pf_batch_destroy(pf_batch* b) {
 
 int pf_step_batch(pf_filter* const* filters, int32_t n, const double* y_each) {
     pf_batch* b = nullptr;
-    int rc = pf_batch_create(filters, n, 1, &b);
+    int rc = pf_batch_create(filters, n, n, 1, &b);
     if (rc != PF_OK) return rc;
     rc = pf_batch_step(b, y_each, 1);
     const int rc2 = pf_batch_destroy(b);

@@ -122,11 +122,13 @@ struct StepArgs {
 
 // Device-side progress of a batch of filters stepped together.
 struct BatchState {
-    uint64_t step;    // steps completed; selects the argument block of the next step
-    uint64_t ticket;  // global tile ticket of the running step
-    uint32_t done;    // scan work-groups finished in the running step
-    uint32_t ring;    // argument blocks in the ring (steps that can be queued)
-    uint64_t pad[5];
+    uint64_t step;      // steps completed; selects the argument block of the next step
+    uint64_t ticket;    // global tile ticket of the running step
+    uint32_t done;      // scan work-groups finished in the running step
+    uint32_t ring;      // argument blocks in the ring (steps that can be queued)
+    int32_t n_filters;  // current members (argument blocks hold `capacity` entries)
+    int32_t capacity;
+    uint64_t pad[4];
 };
 
 }  // namespace pf

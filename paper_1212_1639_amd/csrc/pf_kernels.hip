@@ -736,11 +736,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
 template <int MODEL, typename R, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void k_step_batch(const StepArgs* __restrict__ descs,
                                                       const int32_t* __restrict__ base,
-                                                      int32_t n_filters, BatchState* bs) {
+                                                      BatchState* bs) {
     __shared__ StepSmem<BLOCK, IPT> sm;
     const uint64_t step = __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t n_filters = bs->n_filters;
+    if (n_filters <= 0) return;
     const int64_t total = base[n_filters];
-    const StepArgs* d = descs + (step % static_cast<uint64_t>(bs->ring)) * n_filters;
+    const StepArgs* d = descs + (step % static_cast<uint64_t>(bs->ring)) * bs->capacity;
     while (true) {
         if (threadIdx.x == 0)
             sm.lo = static_cast<int64_t>(__hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
@@ -861,21 +863,25 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const double* agg, in
     scan_tiles(agg, num_tiles, n, ts, ab, hint, tot, st);
 }
 
-// The batch's scans: work-group f scans filter f (if it weighted this step);
-// the last work-group to finish advances the batch's step counter and resets
-// its tile ticket.
+// The batch's scans: work-group g scans filters g, g + grid, ... (those that
+// weighted this step); the last work-group to finish advances the batch's
+// step counter and resets its tile ticket.
 __global__ __launch_bounds__(kScanBlock) void k_scan_batch(const StepArgs* __restrict__ descs,
-                                                           int32_t n_filters, BatchState* bs) {
+                                                           BatchState* bs) {
     __shared__ uint32_t s_last;
     const uint64_t step = __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const StepArgs& A = descs[(step % static_cast<uint64_t>(bs->ring)) * n_filters + blockIdx.x];
-    if (A.flags & kWeight)
-        scan_tiles(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out, A.tot_out, A.st);
-    __syncthreads();
+    const int32_t n_filters = bs->n_filters;
+    const StepArgs* d = descs + (step % static_cast<uint64_t>(bs->ring)) * bs->capacity;
+    for (int32_t f = blockIdx.x; f < n_filters; f += gridDim.x) {
+        const StepArgs& A = d[f];
+        if (A.flags & kWeight)
+            scan_tiles(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out, A.tot_out, A.st);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        const uint32_t d = __hip_atomic_fetch_add(&bs->done, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (d == static_cast<uint32_t>(n_filters - 1)) ? 1u : 0u;
+        const uint32_t dn = __hip_atomic_fetch_add(&bs->done, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (dn == gridDim.x - 1) ? 1u : 0u;
         if (s_last) {
             __hip_atomic_store(&bs->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bs->ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1164,8 +1170,9 @@ hipError_t launch_step(int model, bool fp64, int ipt, const StepArgs& a, int gri
 template <int MODEL, typename R, int IPT>
 static hipError_t launch_batch_t(const StepArgs* descs, const int32_t* base, int32_t n_filters,
                                  BatchState* bs, int grid, hipStream_t s) {
+    (void)n_filters;
     hipLaunchKernelGGL((k_step_batch<MODEL, R, 256, IPT>), dim3(grid), dim3(256), 0, s, descs, base,
-                       n_filters, bs);
+                       bs);
     return hipGetLastError();
 }
 
@@ -1197,7 +1204,9 @@ hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, co
                          : launch_batch_m<kSVPL, float>(ipt, descs, base, n_filters, bs, grid, s); break;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_batch, dim3(n_filters), dim3(kScanBlock), 0, s, descs, n_filters, bs);
+    // n_filters here is the batch's capacity: the scan grid covers it
+    const int sgrid = n_filters < 256 ? (n_filters > 0 ? n_filters : 1) : 256;
+    hipLaunchKernelGGL(k_scan_batch, dim3(sgrid), dim3(kScanBlock), 0, s, descs, bs);
     return hipGetLastError();
 }
 

@@ -27,8 +27,8 @@ MODEL_NAMES = {"ll_pf": LL_PF, "ll_pl": LL_PL, "sv_pf": SV_PF, "sv_pl": SV_PL}
 
 # every symbol include/pf.h declares
 EXPORTS = ["pf_fields", "pf_workspace_bytes", "pf_create", "pf_step", "pf_loglik", "pf_moments",
-           "pf_destroy", "pf_last_error", "pf_batch_create", "pf_batch_step", "pf_batch_destroy",
-           "pf_step_batch", "pf_debug_search", "pf_debug_particles"]
+           "pf_destroy", "pf_last_error", "pf_batch_create", "pf_batch_update", "pf_batch_step",
+           "pf_batch_destroy", "pf_step_batch", "pf_debug_search", "pf_debug_particles"]
 
 
 class PFError(RuntimeError):
@@ -89,12 +89,14 @@ def lib():
         L.pf_last_error.restype = ctypes.c_char_p
         L.pf_debug_search.argtypes = [vp, vp, i64, i64, i32, vp, vp]
         L.pf_debug_particles.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(i64)]
-        L.pf_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+        L.pf_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)]
+        L.pf_batch_update.argtypes = [vp, ctypes.POINTER(vp), i32]
         L.pf_batch_step.argtypes = [vp, ctypes.POINTER(d), i64]
         L.pf_batch_destroy.argtypes = [vp]
         L.pf_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(d)]
         for name in ("pf_create", "pf_step", "pf_loglik", "pf_moments", "pf_destroy",
-                     "pf_batch_create", "pf_batch_step", "pf_batch_destroy", "pf_step_batch",
+                     "pf_batch_create", "pf_batch_update", "pf_batch_step", "pf_batch_destroy",
+                     "pf_step_batch",
                      "pf_debug_search", "pf_debug_particles"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -197,14 +199,24 @@ class Filter:
 class Batch:
     """Filters stepped together (one persistent launch per step, graph-replayed)."""
 
-    def __init__(self, filters, ring=64):
+    def __init__(self, filters, ring=64, capacity=0):
         self.filters = list(filters)
         arr = (ctypes.c_void_p * len(self.filters))(*[f._h.value for f in self.filters])
         self._h = ctypes.c_void_p()
-        _check(lib().pf_batch_create(arr, len(self.filters), ring, ctypes.byref(self._h)))
+        _check(lib().pf_batch_create(arr, len(self.filters), capacity, ring,
+                                     ctypes.byref(self._h)))
+
+    def update(self, filters):
+        """Replace the members (filters may join at any stage or leave)."""
+        self.filters = list(filters)
+        arr = (ctypes.c_void_p * max(1, len(self.filters)))(
+            *[f._h.value for f in self.filters])
+        _check(lib().pf_batch_update(self._h, arr, len(self.filters)))
 
     def step(self, y):
         """y: (n_steps, n_filters) observations, or (n_filters,) for one step."""
+        if not self.filters:
+            return
         y = np.ascontiguousarray(y, dtype=np.float64)
         if y.ndim == 1:
             y = y[None, :]
