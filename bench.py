@@ -43,6 +43,34 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per full cycle of the dominant kernel, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE runs (KiB per dispatch) scaled by the counters' reading for a
+# 1 GiB device copy (fetch x 2.0, write x 1.0).  Valid only for the kernel
+# sources they were taken with (hash of the three files below); otherwise
+# the bench reports null.
+COUNTER_SOURCES = ("pf_kernels.hip", "pf_models.hpp", "pf_internal.h")
+TRAFFIC = {
+    "ll_pl_2p20": dict(fetch_kib=13382.34, write_kib=24960.0, sources="8525a0af09dc4e6f"),
+    "sv_pl_2p26": dict(fetch_kib=947693.16, write_kib=1847296.0, sources="8525a0af09dc4e6f"),
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1212_1639_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(workload):
+    t = TRAFFIC.get(workload)
+    if t is None or t["sources"] != kernel_sources_hash():
+        return None
+    return (t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0
 METRIC = "particle-steps/sec @1 MI355X (batched vs plain), %HBM peak; p50/p99 step latency"
 
 WORKLOADS = {
@@ -305,26 +333,23 @@ def main():
         del warm
 
     f = pf.Filter(cfg, stream=stream)
+    f.timing_start(K)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record(stream)
     f.step(y[:K])
-    ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    ev_ms = ev0.elapsed_time(ev1)
+    kern_ms, launches = f.timing_read()
     loglik = f.loglik()
     mom = f.moments()
     f.close()
 
     n = w["n"]
     value = n * K / wall
-    # one cycle launch per step: its average duration from the events on the
-    # filter's stream (includes the launch gaps between consecutive cycles)
-    kern_s = ev_ms * 1e-3 / K
+    # one cycle-kernel launch per step, each bracketed by a pair of HIP events
+    # on the filter's stream: the kernel's average duration
+    kern_s = kern_ms * 1e-3 / max(1, launches)
     bytes_launch = w["bytes_per_particle"] * n
     achieved = bytes_launch / kern_s / 1e9
     out = {
@@ -343,7 +368,7 @@ def main():
         "config": {"workload": args.workload, "model": w["model"], "n_particles": n,
                    "T": w["T"], "scheme": w["scheme"], "form": "plain"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(args.workload),
                      "kernel": "k_step", "kernel_avg_us": kern_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_launch},
         "loglik": loglik,

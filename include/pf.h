@@ -245,6 +245,48 @@ int pf_debug_search(const double* cdf_dev, const double* u_dev, int64_t n, int64
  * (L00 = p0 + t and the shape a_s + t/2 are the same for every particle). */
 int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_out);
 
+/* Autotuner (a runtime aid, not part of the method): picks the tile size
+ * (cfg->items_per_thread), the search strategy (cfg->strategy) and the CDF
+ * scan (the PF_FLAG_LOOKBACK_SCAN bit of cfg->flags) for cfg by timing
+ * candidates on hip_stream: first items_per_thread in {1, 2, 4, 8} with the
+ * library's default strategy and the tile scan, then every strategy valid at
+ * the best tile size, then the look-back scan.  Each candidate is a
+ * temporary filter (library-allocated workspace) stepped over y[0..n_obs)
+ * (host array, n_obs >= 3; the first two steps are warm-up).  Other fields
+ * of *cfg are kept; the choice is written back into *cfg and cached per
+ * (device, model, precision, scheme, ancestor flag, ceil(log2 N)), so a later
+ * call for a similar configuration returns at once.  *ms_per_step (if not
+ * NULL) receives the winner's time per step.  Synchronises hip_stream.
+ * The random draws do not depend on the choice; the CDF's summation order
+ * (tile boundaries) does, so results agree to rounding.  Errors: PF_EINVAL
+ * (invalid cfg, n_obs < 3, non-finite y), PF_ENOMEM (no candidate fits),
+ * PF_EDEVICE. */
+int pf_autotune(pf_config* cfg, const double* y, int64_t n_obs, void* hip_stream,
+                double* ms_per_step);
+
+/* Autotuner of a batch: the common items_per_thread in {1, 2, 4, 8} (with
+ * the default strategy), then bisection instead of the default search at
+ * that size, timed by stepping temporary copies of the n filters cfgs[0..n)
+ * as one batch (pf_batch_step) over y[s * n + f], s < n_obs (n_obs >= 3).
+ * Writes items_per_thread and strategy into every cfgs[k]; batched filters
+ * use the tile scan (PF_FLAG_LOOKBACK_SCAN set is PF_EINVAL).  Not cached.
+ * Synchronises hip_stream.  Errors as pf_autotune. */
+int pf_autotune_batch(pf_config* cfgs, int32_t n, const double* y, int64_t n_obs,
+                      void* hip_stream, double* ms_per_step);
+
+/* Kernel timing, a measurement aid (not part of the method).
+ * pf_timing_start synchronises f's stream and arms max_launches
+ * (1 <= max_launches <= 2^20) pairs of HIP events: each of f's next
+ * cycle-kernel launches, up to that many, is bracketed by one pair on f's
+ * stream (the CDF tile scan that follows a weighting launch is outside the
+ * bracket).  pf_timing_read synchronises, returns in *total_ms the summed
+ * event-to-event time of the bracketed launches and in *launches their
+ * count, and disarms.  Arming again discards earlier pairs.  The events are
+ * owned by the handle and released by pf_timing_read or pf_destroy.
+ * Errors: PF_EINVAL (null argument, bad count), PF_EDEVICE. */
+int pf_timing_start(pf_filter* f, int64_t max_launches);
+int pf_timing_read(pf_filter* f, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -273,3 +273,30 @@ def sv_theta(post, z_g, u_g, z3, z4, seed=0, j=0, t=0, fp32=False):
                               ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.or_sv_theta(_dp(p), z_g, u_g, z3, z4, seed, j, t, int(fp32), _dp(th))
     return th
+
+
+def step_slots(cfg, state0, t0, y_prev, y, slots):
+    """One step t0 + 1 from the particles ``state0`` (fields x N, after t0
+    steps) for the output slots ``slots`` only: returns (ancestors (k,),
+    new fields (F, k)).  ``y_prev`` is y_{t0} (weights of the models that
+    weight after propagating), ``y`` is y_{t0+1}.  Same per-slot arithmetic
+    as ``run``, for checking outputs at sizes a whole run would take too
+    long for."""
+    N = cfg.n
+    F = FIELDS[cfg.model]
+    s0 = np.ascontiguousarray(state0, dtype=np.float64).reshape(F, N)
+    sl = np.ascontiguousarray(slots, dtype=np.int64)
+    k = sl.size
+    anc = np.zeros(k, dtype=np.int64)
+    st = np.zeros((F, k))
+    L = lib()
+    L.or_step_slots.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double),
+                                ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    L.or_step_slots.restype = ctypes.c_int
+    rc = L.or_step_slots(ctypes.byref(cfg), _dp(s0), int(t0), float(y_prev), float(y), _ip(sl), k,
+                         _ip(anc), _dp(st))
+    if rc == -2:
+        raise ValueError("or_step_slots: bad arguments")
+    return anc, st

@@ -240,23 +240,29 @@ void or_resample(const double* q, int64_t n, const double* u, int64_t m, int met
  * j is 0-based, so stratum j is [j/N, (j+1)/N]. */
 enum { OR_MULTINOMIAL = 0, OR_STRATIFIED = 1, OR_SYSTEMATIC = 2 };
 
-void or_uniforms(int scheme, uint64_t seed, uint32_t t, int64_t n, double* u)
+/* Uniform u_j of slot j; U_sys is the systematic offset of time t. */
+static double slot_uniform(int scheme, uint64_t seed, uint32_t t, int64_t n, int64_t j,
+                           double U_sys)
 {
     uint32_t w[4];
-    double U = 0.0;
-    if (scheme == OR_SYSTEMATIC) {
-        words(seed, 0, t, ST_SYSTEMATIC, 0, w);
-        U = or_u32(w[0]);
-    }
-    for (int64_t j = 0; j < n; ++j) {
-        if (scheme == OR_SYSTEMATIC) {
-            u[j] = ((double)j + U) / (double)n;
-        } else {
-            words(seed, (uint32_t)j, t, ST_STEP, 0, w);
-            double Uj = or_u32(w[0]);
-            u[j] = scheme == OR_STRATIFIED ? ((double)j + Uj) / (double)n : Uj;
-        }
-    }
+    if (scheme == OR_SYSTEMATIC) return ((double)j + U_sys) / (double)n;
+    words(seed, (uint32_t)j, t, ST_STEP, 0, w);
+    double Uj = or_u32(w[0]);
+    return scheme == OR_STRATIFIED ? ((double)j + Uj) / (double)n : Uj;
+}
+
+static double systematic_offset(int scheme, uint64_t seed, uint32_t t)
+{
+    uint32_t w[4];
+    if (scheme != OR_SYSTEMATIC) return 0.0;
+    words(seed, 0, t, ST_SYSTEMATIC, 0, w);
+    return or_u32(w[0]);
+}
+
+void or_uniforms(int scheme, uint64_t seed, uint32_t t, int64_t n, double* u)
+{
+    const double U = systematic_offset(scheme, seed, t);
+    for (int64_t j = 0; j < n; ++j) u[j] = slot_uniform(scheme, seed, t, n, j, U);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -311,6 +317,33 @@ static double log_normal_pdf(double y, double mean, double var)
  *   logw (optional) [(t-1)*N + i] log-weight of particle i at step t.
  * Returns 0, or -1 when every weight of some step is zero or not finite. */
 
+/* Propagation of one output slot j at time t from its resampled
+ * ancestor's fields zk[0..F-1] (F = or_fields(model)); writes the slot's new
+ * fields to out[0..F-1].  The filters below call these for every slot; the
+ * sampled step (or_step_slots) calls them for a few. */
+
+/* Local level, known variances: x_t = x~ + sqrt(sigma_w2) Z, Z from words
+ * 1, 2 of ST_STEP (j, t). */
+static void ll_pf_slot(const or_config* c, const double* zk, uint32_t j, uint32_t t, double* out)
+{
+    uint32_t w[4];
+    double z[2];
+    words(c->seed, j, t, ST_STEP, 0, w);
+    or_box_muller(unif(w[1], c->fp32_words), unif(w[2], c->fp32_words), z);
+    out[0] = zk[0] + sqrt(c->sigma_w2) * z[0];
+}
+
+/* Stochastic volatility, known parameters: x_t = mu + phi (x~ - mu) + sigma Z. */
+static void sv_pf_slot(const or_config* c, const double* zk, uint32_t j, uint32_t t, double* out)
+{
+    uint32_t w[4];
+    double z[2];
+    const double sd = sqrt(c->sigma2);
+    words(c->seed, j, t, ST_STEP, 0, w);
+    or_box_muller(unif(w[1], c->fp32_words), unif(w[2], c->fp32_words), z);
+    out[0] = c->mu + c->phi * (zk[0] - c->mu) + sd * z[0];
+}
+
 /* Local-level bootstrap particle filter (Section 2, Algorithm "Particle
  * Filtering"; model of Section 4, equation (trend+noise), known variances).
  * Step 0: x~_0 ~ N(x0_mean, x0_var).  At t = 1 there is nothing to
@@ -357,11 +390,7 @@ static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* log
             or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
             or_resample(q, N, u, N, c->search, a);
         }
-        for (int64_t j = 0; j < N; ++j) {
-            words(c->seed, (uint32_t)j, (uint32_t)t, ST_STEP, 0, w);
-            or_box_muller(unif(w[1], fp32), unif(w[2], fp32), z);
-            xn[j] = x[a[j]] + sqrt(c->sigma_w2) * z[0];
-        }
+        for (int64_t j = 0; j < N; ++j) ll_pf_slot(c, &x[a[j]], (uint32_t)j, (uint32_t)t, &xn[j]);
         memcpy(x, xn, sizeof(double) * N);
         for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[r], x[i], c->sigma_v2);
         double M, S;
@@ -404,7 +433,6 @@ static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* log
     uint32_t w[4];
     double z[2];
     int rc = 0;
-    const double sd = sqrt(c->sigma2);
     for (int64_t i = 0; i < N && !state0; ++i) {
         words(c->seed, (uint32_t)i, 0, ST_INIT, 0, w);
         or_box_muller(unif(w[0], fp32), unif(w[1], fp32), z);
@@ -427,11 +455,7 @@ static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* log
             or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
             or_resample(q, N, u, N, c->search, a);
         }
-        for (int64_t j = 0; j < N; ++j) {
-            words(c->seed, (uint32_t)j, (uint32_t)t, ST_STEP, 0, w);
-            or_box_muller(unif(w[1], fp32), unif(w[2], fp32), z);
-            xn[j] = c->mu + c->phi * (x[a[j]] - c->mu) + sd * z[0];
-        }
+        for (int64_t j = 0; j < N; ++j) sv_pf_slot(c, &x[a[j]], (uint32_t)j, (uint32_t)t, &xn[j]);
         memcpy(x, xn, sizeof(double) * N);
         for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[r], 0.0, exp(x[i]));
         double M, S;
@@ -484,6 +508,37 @@ static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* log
  *   mean of the drawn sigma_v^2 and sigma_w^2 (Section 2, posterior
  *   statistics from the theta sample), and the Rao-Blackwell means
  *   b/(a - 1) of the two IG posteriors. */
+/* Steps 2-4 of particle learning for slot j at time t, from the resampled
+ * particle zk = (x~, b_v, b_w, sigma_v^2, sigma_w^2) and y_t. */
+static void ll_pl_slot(const or_config* c, const double* zk, uint32_t j, uint32_t t, double yt,
+                       double* out)
+{
+    const int fp32 = c->fp32_words;
+    uint32_t w[4];
+    double g[2];
+    const double av = c->a_v + 0.5 * (double)t, aw = c->a_w + 0.5 * (double)t;
+    const double xp = zk[0], sv2 = zk[3], sw2 = zk[4];
+    words(c->seed, j, t, ST_STEP, 0, w);
+    or_box_muller(unif(w[1], fp32), unif(w[2], fp32), g);
+    double z_x = g[0], z_v = g[1], u_v = unif(w[3], fp32);
+    words(c->seed, j, t, ST_STEP2, 0, w);
+    or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
+    double z_w = g[0], u_w = unif(w[2], fp32);
+    /* Step 2 */
+    double V = 1.0 / (1.0 / sw2 + 1.0 / sv2);
+    double m = V * (xp / sw2 + yt / sv2);
+    double xt = m + sqrt(V) * z_x;
+    /* Step 3 */
+    double bv = zk[1] + 0.5 * (yt - xt) * (yt - xt);
+    double bw = zk[2] + 0.5 * (xt - xp) * (xt - xp);
+    /* Step 4 */
+    out[0] = xt;
+    out[1] = bv;
+    out[2] = bw;
+    out[3] = bv / or_gamma_mt(av, z_v, u_v, c->seed, j, t, 0, fp32);
+    out[4] = bw / or_gamma_mt(aw, z_w, u_w, c->seed, j, t, 1, fp32);
+}
+
 static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* loglik,
                      double* mom, int64_t* anc_out, double* state_out, double* logw_out,
                      const double* state0, int64_t t0, double y_prev)
@@ -529,27 +584,10 @@ static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* log
         or_resample(q, N, u, N, c->search, a);
         const double av = c->a_v + 0.5 * (double)t, aw = c->a_w + 0.5 * (double)t;
         for (int64_t j = 0; j < N; ++j) {
-            const int64_t k = a[j];
-            const double xp = z[0 * N + k], sv2 = z[3 * N + k], sw2 = z[4 * N + k];
-            words(c->seed, (uint32_t)j, (uint32_t)t, ST_STEP, 0, w);
-            or_box_muller(unif(w[1], fp32), unif(w[2], fp32), g);
-            double z_x = g[0], z_v = g[1], u_v = unif(w[3], fp32);
-            words(c->seed, (uint32_t)j, (uint32_t)t, ST_STEP2, 0, w);
-            or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
-            double z_w = g[0], u_w = unif(w[2], fp32);
-            /* Step 2 */
-            double V = 1.0 / (1.0 / sw2 + 1.0 / sv2);
-            double m = V * (xp / sw2 + yt / sv2);
-            double xt = m + sqrt(V) * z_x;
-            /* Step 3 */
-            double bv = z[1 * N + k] + 0.5 * (yt - xt) * (yt - xt);
-            double bw = z[2 * N + k] + 0.5 * (xt - xp) * (xt - xp);
-            /* Step 4 */
-            zn[0 * N + j] = xt;
-            zn[1 * N + j] = bv;
-            zn[2 * N + j] = bw;
-            zn[3 * N + j] = bv / or_gamma_mt(av, z_v, u_v, c->seed, (uint32_t)j, (uint32_t)t, 0, fp32);
-            zn[4 * N + j] = bw / or_gamma_mt(aw, z_w, u_w, c->seed, (uint32_t)j, (uint32_t)t, 1, fp32);
+            double zk[5], out[5];
+            for (int f = 0; f < F; ++f) zk[f] = z[f * N + a[j]];
+            ll_pl_slot(c, zk, (uint32_t)j, (uint32_t)t, yt, out);
+            for (int f = 0; f < F; ++f) zn[f * N + j] = out[f];
         }
         memcpy(z, zn, sizeof(double) * N * F);
         double sx = 0, sxx = 0, sv = 0, sw = 0, rv = 0, rw = 0;
@@ -643,6 +681,40 @@ void or_sv_theta(const double post[7], double z_g, double u_g, double z3, double
     theta[2] = s2;
 }
 
+/* Step t of stochastic-volatility particle learning for slot j from the
+ * resampled particle zk = (x~, n, S1, S11, Sy, S1y, Syy): theta from the
+ * posterior of the sums, x_t, the sums updated with the pair (x~, x_t).
+ * theta[] receives the draw, *rb the Rao-Blackwell mean d/(a-1) of sigma^2
+ * after the update. */
+static void sv_pl_slot(const or_config* c, const double* zk, uint32_t j, uint32_t t,
+                       double* out, double theta[3], double* rb)
+{
+    const int fp32 = c->fp32_words;
+    uint32_t w[4];
+    double g[2];
+    const double xp = zk[0];
+    double sums[6], post[7];
+    for (int f = 0; f < 6; ++f) sums[f] = zk[f + 1];
+    or_sv_posterior(c, sums, post);
+    words(c->seed, j, t, ST_STEP, 0, w);
+    or_box_muller(unif(w[1], fp32), unif(w[2], fp32), g);
+    double z_g = g[0], z_x = g[1], u_g = unif(w[3], fp32);
+    words(c->seed, j, t, ST_STEP2, 0, w);
+    or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
+    or_sv_theta(post, z_g, u_g, g[0], g[1], c->seed, j, t, fp32, theta);
+    double xt = theta[0] + theta[1] * xp + sqrt(theta[2]) * z_x;
+    sums[0] += 1.0;
+    sums[1] += xp;
+    sums[2] += xp * xp;
+    sums[3] += xt;
+    sums[4] += xp * xt;
+    sums[5] += xt * xt;
+    out[0] = xt;
+    for (int f = 0; f < 6; ++f) out[f + 1] = sums[f];
+    or_sv_posterior(c, sums, post);
+    *rb = post[6] / (post[5] - 1.0);
+}
+
 /* Stochastic-volatility particle learning (not in the paper; Storvik-type
  * order: propagate, weight, resample, as in the bootstrap cycle).
  * Transition x_t = alpha + beta x_{t-1} + sigma Z, i.e. alpha = mu (1 - phi),
@@ -706,30 +778,11 @@ static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* log
             or_resample(q, N, u, N, c->search, a);
         }
         for (int64_t j = 0; j < N; ++j) {
-            const int64_t k = a[j];
-            const double xp = z[0 * N + k];
-            double sums[6], post[7], theta[3];
-            for (int f = 0; f < 6; ++f) sums[f] = z[(f + 1) * N + k];
-            or_sv_posterior(c, sums, post);
-            words(c->seed, (uint32_t)j, (uint32_t)t, ST_STEP, 0, w);
-            or_box_muller(unif(w[1], fp32), unif(w[2], fp32), g);
-            double z_g = g[0], z_x = g[1], u_g = unif(w[3], fp32);
-            words(c->seed, (uint32_t)j, (uint32_t)t, ST_STEP2, 0, w);
-            or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
-            or_sv_theta(post, z_g, u_g, g[0], g[1], c->seed, (uint32_t)j, (uint32_t)t, fp32,
-                        theta);
-            double xt = theta[0] + theta[1] * xp + sqrt(theta[2]) * z_x;
-            sums[0] += 1.0;
-            sums[1] += xp;
-            sums[2] += xp * xp;
-            sums[3] += xt;
-            sums[4] += xp * xt;
-            sums[5] += xt * xt;
-            zn[0 * N + j] = xt;
-            for (int f = 0; f < 6; ++f) zn[(f + 1) * N + j] = sums[f];
+            double zk[7], out[7], theta[3];
+            for (int f = 0; f < F; ++f) zk[f] = z[f * N + a[j]];
+            sv_pl_slot(c, zk, (uint32_t)j, (uint32_t)t, out, theta, &rb[j]);
+            for (int f = 0; f < F; ++f) zn[f * N + j] = out[f];
             th[0 * N + j] = theta[0]; th[1 * N + j] = theta[1]; th[2 * N + j] = theta[2];
-            or_sv_posterior(c, sums, post);
-            rb[j] = post[6] / (post[5] - 1.0);
         }
         memcpy(z, zn, sizeof(double) * N * F);
         for (int64_t i = 0; i < N; ++i) lw[i] = log_normal_pdf(y[r], 0.0, exp(z[i]));
@@ -786,4 +839,63 @@ int or_run(const or_config* c, const double* y, int64_t T, double* loglik, doubl
            int64_t* anc_out, double* state_out, double* logw_out)
 {
     return or_run_from(c, NULL, 0, 0.0, y, T, loglik, mom, anc_out, state_out, logw_out);
+}
+
+/* One step t = t0 + 1 from the particles state0 (the model's fields after
+ * t0 steps, [f * N + i]), computed only for the output slots
+ * slots[0..k): the resampling CDF over all N particles (weights of y_prev
+ * for the models that weight after propagating, of the predictive
+ * p(y_t | z) for local-level particle learning), each slot's uniform and
+ * ancestor, and the slot's new fields, by the same per-slot arithmetic as
+ * or_run_from.  anc_out[i] and state_out[f * k + i] for slot slots[i];
+ * with t0 = 0 the models that weight after propagating keep every slot's
+ * own particle.  Returns 0, -1 if the weights are degenerate, -2 for bad
+ * arguments. */
+int or_step_slots(const or_config* c, const double* state0, int64_t t0, double y_prev, double y,
+                  const int64_t* slots, int64_t k, int64_t* anc_out, double* state_out)
+{
+    if (!c || c->n < 1 || !state0 || t0 < 0 || k < 0 || (k > 0 && (!slots || !anc_out || !state_out)))
+        return -2;
+    const int64_t N = c->n;
+    const int F = or_fields(c->model);
+    const uint32_t t = (uint32_t)(t0 + 1);
+    for (int64_t i = 0; i < k; ++i)
+        if (slots[i] < 0 || slots[i] >= N) return -2;
+    int rc = 0;
+    const int resample = c->model == OR_LL_PL || t0 >= 1;
+    if (resample) {
+        double* lw = (double*)malloc(sizeof(double) * N);
+        double* q = (double*)malloc(sizeof(double) * N);
+        double* u = (double*)malloc(sizeof(double) * (k > 0 ? k : 1));
+        for (int64_t i = 0; i < N; ++i) {
+            const double x = state0[i];
+            switch (c->model) {
+            case OR_LL_PF: lw[i] = log_normal_pdf(y_prev, x, c->sigma_v2); break;
+            case OR_LL_PL: lw[i] = log_normal_pdf(y, x, state0[3 * N + i] + state0[4 * N + i]); break;
+            default: lw[i] = log_normal_pdf(y_prev, 0.0, exp(x)); break;
+            }
+        }
+        double M, S;
+        or_cdf(lw, N, q, &M, &S);
+        if (!(S > 0.0) || !isfinite(S) || !isfinite(M)) rc = -1;
+        const double U = systematic_offset(c->scheme, c->seed, t);
+        for (int64_t i = 0; i < k; ++i) u[i] = slot_uniform(c->scheme, c->seed, t, N, slots[i], U);
+        or_resample(q, N, u, k, c->search, anc_out);
+        free(lw); free(q); free(u);
+    } else {
+        for (int64_t i = 0; i < k; ++i) anc_out[i] = slots[i];
+    }
+    for (int64_t i = 0; i < k; ++i) {
+        double zk[7], out[7], theta[3], rb;
+        for (int f = 0; f < F; ++f) zk[f] = state0[f * N + anc_out[i]];
+        const uint32_t j = (uint32_t)slots[i];
+        switch (c->model) {
+        case OR_LL_PF: ll_pf_slot(c, zk, j, t, out); break;
+        case OR_LL_PL: ll_pl_slot(c, zk, j, t, y, out); break;
+        case OR_SV_PF: sv_pf_slot(c, zk, j, t, out); break;
+        default: sv_pl_slot(c, zk, j, t, out, theta, &rb); break;
+        }
+        for (int f = 0; f < F; ++f) state_out[f * k + i] = out[f];
+    }
+    return rc;
 }

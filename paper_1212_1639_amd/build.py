@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libpf_mi355x.so")
-SOURCES = ["pf_kernels.hip", "pf_api.cpp"]
+SOURCES = ["pf_kernels.hip", "pf_api.cpp", "pf_tune.cpp"]
 ARCH = "gfx950"
 
 

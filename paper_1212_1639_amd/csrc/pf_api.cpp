@@ -15,8 +15,10 @@
 namespace pf {
 hipError_t launch_step(int model, bool fp64, int ipt, const StepArgs& a, int grid, hipStream_t s,
                        bool init);
-hipError_t launch_scan_tiles(const double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
-                             int32_t* hint, Totals* tot, DevState* st, hipStream_t s);
+hipError_t launch_scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
+                             int32_t* hint, Totals* tot, DevState* st, double* chunk,
+                             hipStream_t s);
+int32_t scan_chunks(int32_t num_tiles);
 hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int32_t* base,
                         int32_t n_filters, BatchState* bs, int grid, hipStream_t s);
 int batch_grid(int model, bool fp64, int ipt);
@@ -39,6 +41,14 @@ int fail(int code, const std::string& msg) {
 int hip_fail(hipError_t e, const char* what) {
     return fail(PF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+}  // namespace
+
+namespace pf {
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace pf
+
+namespace {
 
 constexpr int kBlock = 256;
 constexpr size_t kAlign = 256;
@@ -77,7 +87,7 @@ struct Layout {
     int ipt = 0, ts = 0, num_tiles = 0, fields = 0, rsz = 0, strategy = 0;
     int64_t pitch = 0;
     size_t rec[2], c[2], samp[2], tiles[2], tot[2], status, state, partials, anc, agg, ab, hint,
-        total;
+        chunk, total;
     bool lookback = false;
 };
 
@@ -174,6 +184,8 @@ int plan(const pf_config* c, Layout* L) {
     L->agg = take(sizeof(double) * 2 * L->num_tiles);
     L->ab = take(sizeof(pf::TileAB) * L->num_tiles);
     L->hint = take(sizeof(int32_t) * (L->num_tiles + 1));
+    const int64_t chunks = pf::scan_chunks(L->num_tiles);
+    L->chunk = take(sizeof(double) * (3 * chunks + 1));
     L->lookback = (c->flags & PF_FLAG_LOOKBACK_SCAN) != 0;
     L->total = off;
     return PF_OK;
@@ -219,6 +231,9 @@ struct pf_filter {
     uint32_t epoch = 0;      // look-back tag of the latest weighting launch
     int32_t weighted_partials = 0;
     pf::ModelParams mp;
+    // kernel timing: event pairs bracketing the cycle-kernel launches
+    std::vector<hipEvent_t> tev;
+    int64_t timed = 0;
 
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -301,13 +316,21 @@ struct pf_filter {
     }
 
     int run(const pf::StepArgs& a) {
+        const bool timing = 2 * timed + 1 < static_cast<int64_t>(tev.size());
+        if (timing && hipEventRecord(tev[2 * timed], stream) != hipSuccess)
+            return hip_fail(hipGetLastError(), "timing event");
         hipError_t e = pf::launch_step(cfg.model, cfg.precision == PF_FP64, L.ipt, a, L.num_tiles,
                                        stream, false);
         if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        if (timing) {
+            if (hipEventRecord(tev[2 * timed + 1], stream) != hipSuccess)
+                return hip_fail(hipGetLastError(), "timing event");
+            ++timed;
+        }
         if ((a.flags & pf::kWeight) && !L.lookback) {
             e = pf::launch_scan_tiles(a.agg_out, L.num_tiles, cfg.n_particles, L.ts,
                                       at<pf::TileAB>(L.ab), at<int32_t>(L.hint), a.tot_out, a.st,
-                                      stream);
+                                      at<double>(L.chunk), stream);
             if (e != hipSuccess) return hip_fail(e, "tile scan launch");
         }
         return PF_OK;
@@ -448,9 +471,55 @@ int pf_moments(pf_filter* f, double* out, int32_t n_out) {
     return PF_OK;
 }
 
+static void release_timing(pf_filter* f) {
+    for (hipEvent_t ev : f->tev) hipEventDestroy(ev);
+    f->tev.clear();
+    f->timed = 0;
+}
+
+int pf_timing_start(pf_filter* f, int64_t max_launches) {
+    if (!f) return fail(PF_EINVAL, "null filter");
+    if (max_launches < 1 || max_launches > (1 << 20))
+        return fail(PF_EINVAL, "max_launches must be in [1, 2^20]");
+    hipError_t e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_timing_start synchronise");
+    release_timing(f);
+    f->tev.resize(static_cast<size_t>(2 * max_launches));
+    for (size_t i = 0; i < f->tev.size(); ++i) {
+        e = hipEventCreate(&f->tev[i]);
+        if (e != hipSuccess) {
+            f->tev.resize(i);
+            release_timing(f);
+            return hip_fail(e, "pf_timing_start event");
+        }
+    }
+    return PF_OK;
+}
+
+int pf_timing_read(pf_filter* f, double* total_ms, int64_t* launches) {
+    if (!f || !total_ms || !launches) return fail(PF_EINVAL, "null argument");
+    hipError_t e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_timing_read synchronise");
+    double sum = 0.0;
+    for (int64_t k = 0; k < f->timed; ++k) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, f->tev[2 * k], f->tev[2 * k + 1]);
+        if (e != hipSuccess) {
+            release_timing(f);
+            return hip_fail(e, "pf_timing_read elapsed time");
+        }
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = f->timed;
+    release_timing(f);
+    return PF_OK;
+}
+
 int pf_destroy(pf_filter* f) {
     if (!f) return PF_OK;
     hipError_t e = hipStreamSynchronize(f->stream);
+    release_timing(f);
     if (f->owns_ws) hipFree(f->ws);
     delete f;
     if (e != hipSuccess) return hip_fail(e, "pf_destroy synchronise");

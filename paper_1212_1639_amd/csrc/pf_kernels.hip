@@ -766,58 +766,62 @@ __global__ __launch_bounds__(BLOCK) void k_step_batch(const StepArgs* __restrict
 // One work-group of 1024 threads turns the tiles' (m_b, s_b) into
 //   A_b = sum_{b' < b} s_b' e^{m_b' - M} / S  (non-decreasing),
 //   B_b = e^{m_b - M} / S,
-// with M = max_b m_b and S = sum_b s_b e^{m_b - M}, in a fixed order (so the
-// result does not depend on timing); adds M + log(S / n) to the
-// log-likelihood; and writes hint[h] = the tile whose range [A_b, A_{b+1})
-// holds the CDF position h * ts / n, for h = 0..tiles, where the next
-// cycle's tile h starts its search for sorted uniforms.
+// with M = max_b m_b taken first, so that each tile costs one exponential
+// and the prefix is a plain double-precision sum, S = sum_b s_b e^{m_b - M}
+// (fixed order: the result does not depend on timing); adds M + log(S / n)
+// to the log-likelihood; and writes hint[h] = the tile whose range
+// [A_b, A_{b+1}) holds the CDF position h * ts / n, for h = 0..tiles, where
+// the next cycle's tile h starts its search for sorted uniforms.  The
+// tiles' maxima are overwritten (agg[2b] becomes e^{m_b - M}).
 constexpr int kScanBlock = 1024;
 
-__device__ __forceinline__ void scan_tiles(const double* agg, int32_t num_tiles, int64_t n,
-                                           int32_t ts, TileAB* ab, int32_t* hint, Totals* tot,
-                                           DevState* st) {
+__device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts,
+                                           TileAB* ab, int32_t* hint, Totals* tot, DevState* st) {
     constexpr int NW = kScanBlock / kWave;
-    __shared__ double s_m[NW], s_s[NW], s_top[NW];
+    __shared__ double s_red[NW], s_top[NW];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int T = num_tiles;
     const int per = (T + kScanBlock - 1) / kScanBlock;
     const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
-    // 1. each thread folds its chunk
-    Agg part = agg_identity();
-    for (int b = b0; b < b1; ++b) part = agg_combine(part, Agg{agg[2 * b], agg[2 * b + 1]});
-    // 2. exclusive scan of the chunk aggregates: Kogge-Stone in the wave,
-    //    then the waves in order
-    Agg incl = part;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        Agg o{__shfl_up(incl.m, off, kWave), __shfl_up(incl.s, off, kWave)};
-        if (lane >= off) incl = agg_combine(o, incl);
-    }
-    if (lane == kWave - 1) {
-        s_m[wave] = incl.m;
-        s_s[wave] = incl.s;
-    }
+    // 1. M = max_b m_b
+    double mx = -INFINITY;
+    for (int b = b0; b < b1; ++b) mx = fmax(mx, agg[2 * b]);
+    mx = wave_max(mx);
+    if (lane == 0) s_red[wave] = mx;
     __syncthreads();
-    Agg wbase = agg_identity(), total = agg_identity();
-    for (int q = 0; q < NW; ++q) {
-        if (q == wave) wbase = total;
-        total = agg_combine(total, Agg{s_m[q], s_s[q]});
-    }
-    Agg excl{__shfl_up(incl.m, 1, kWave), __shfl_up(incl.s, 1, kWave)};
-    if (lane == 0) excl = agg_identity();
-    excl = agg_combine(wbase, excl);
-    const double M = total.m, S = total.s;
-    const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
-    // 3. normalised affine constants, made non-decreasing (running max over
-    //    the chunk, then over the chunks' maxima)
-    Agg run = excl;
-    double amax = -INFINITY;
+    double M = -INFINITY;
+    for (int q = 0; q < NW; ++q) M = fmax(M, s_red[q]);
+    __syncthreads();
+    // 2. e_b = e^{m_b - M} (one exponential per tile; kept in agg[2b]) and
+    //    the chunk's sum of w_b = s_b e_b, in tile order
+    double part = 0.0;
     for (int b = b0; b < b1; ++b) {
-        const double mb = agg[2 * b], sb = agg[2 * b + 1];
-        double a = (run.m == -INFINITY || !ok) ? 0.0 : run.s * exp(run.m - M) / S;
-        amax = fmax(amax, a);
-        ab[b] = TileAB{amax, (mb == -INFINITY || !ok) ? 0.0 : exp(mb - M) / S};
-        run = agg_combine(run, Agg{mb, sb});
+        const double mb = agg[2 * b];
+        const double eb = (mb == -INFINITY || M == -INFINITY) ? 0.0 : exp(mb - M);
+        agg[2 * b] = eb;
+        part += agg[2 * b + 1] * eb;
+    }
+    // 3. exclusive scan of the chunk sums: in the wave, then the waves in order
+    const double incl = wave_incl_sum(part);
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    double wbase = 0.0, S = 0.0;
+    for (int q = 0; q < NW; ++q) {
+        if (q == wave) wbase = S;
+        S += s_red[q];
+    }
+    double excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = 0.0;
+    excl += wbase;
+    const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
+    // 4. normalised affine constants, made non-decreasing (running max over
+    //    the chunk, then over the chunks' maxima)
+    double run = excl, amax = -INFINITY;
+    for (int b = b0; b < b1; ++b) {
+        const double eb = agg[2 * b];
+        amax = fmax(amax, ok ? run / S : 0.0);
+        ab[b] = TileAB{amax, ok ? eb / S : 0.0};
+        run += agg[2 * b + 1] * eb;
     }
     const double top = wave_incl_max(amax);
     if (lane == kWave - 1) s_top[wave] = top;
@@ -833,7 +837,7 @@ __device__ __forceinline__ void scan_tiles(const double* agg, int32_t num_tiles,
         }
     }
     __syncthreads();
-    // 4. search hints: tile b owns the output tiles h with
+    // 5. search hints: tile b owns the output tiles h with
     //    ceil(A_b n / ts) <= h < ceil(A_{b+1} n / ts); tile 0 starts at h = 0
     //    and the last tile runs to h = tiles.  Every tile reads A_b and
     //    A_{b+1} from the same stored table, so the ranges partition 0..tiles.
@@ -856,11 +860,191 @@ __device__ __forceinline__ void scan_tiles(const double* agg, int32_t num_tiles,
     }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const double* agg, int32_t num_tiles,
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(double* agg, int32_t num_tiles,
                                                            int64_t n, int32_t ts, TileAB* ab,
                                                            int32_t* hint, Totals* tot,
                                                            DevState* st) {
     scan_tiles(agg, num_tiles, n, ts, ab, hint, tot, st);
+}
+
+// ------------------------------------------------------------ chunked tile scan
+// For many tiles the same table comes from three launches over chunks of
+// kScanBlock consecutive tiles, one work-group per chunk, each tile read
+// by one thread (coalesced):
+//   k_scan_chunks: chunk c's (m_c, s_c) = (max_b m_b, sum_b s_b e^{m_b - m_c});
+//   k_scan_top:    M = max_c m_c, the chunks' weights s_c e^{m_c - M}, their
+//                  exclusive prefix P_c (made non-decreasing; S = P_G), the
+//                  totals and the log-likelihood increment M + log(S / n);
+//   k_scan_apply:  tile weights s_b e^{m_b - M}, their exclusive prefix in
+//                  the chunk from P_c, A_b = min(P_c + prefix, P_{c+1}) / S
+//                  made non-decreasing, B_b = e^{m_b - M} / S, and the search
+//                  hints of the chunk's tiles.
+// Clamping every A_b of chunk c to P_{c+1} / S, which is exactly the first
+// A of chunk c + 1, keeps A non-decreasing across chunks although the chunk
+// prefixes and the in-chunk prefixes are rounded separately.  Fixed order
+// throughout: the result does not depend on timing.
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double* s_red) {
+    v = wave_max(v);
+    if (lane_id() == 0) s_red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double r = -INFINITY;
+    for (int q = 0; q < NW; ++q) r = fmax(r, s_red[q]);
+    __syncthreads();
+    return r;
+}
+
+// Exclusive prefix sum in thread order; *total receives the block's sum.
+template <int NW>
+__device__ __forceinline__ double block_excl_sum(double v, double* s_red, double* total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const double incl = wave_incl_sum(v);
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    double base = 0.0, tot = 0.0;
+    for (int q = 0; q < NW; ++q) {
+        if (q == wave) base = tot;
+        tot += s_red[q];
+    }
+    __syncthreads();
+    double ex = __shfl_up(incl, 1, kWave);
+    if (lane == 0) ex = 0.0;
+    *total = tot;
+    return base + ex;
+}
+
+// Largest value of the threads before this one (-inf for thread 0).
+template <int NW>
+__device__ __forceinline__ double block_excl_max(double v, double* s_red) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const double incl = wave_incl_max(v);
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    double carry = -INFINITY;
+    for (int q = 0; q < wave; ++q) carry = fmax(carry, s_red[q]);
+    __syncthreads();
+    double ex = __shfl_up(incl, 1, kWave);
+    if (lane == 0) ex = -INFINITY;
+    return fmax(ex, carry);
+}
+
+// Inclusive running maximum in thread order.
+template <int NW>
+__device__ __forceinline__ double block_incl_max(double v, double* s_red) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const double incl = wave_incl_max(v);
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    double carry = -INFINITY;
+    for (int q = 0; q < wave; ++q) carry = fmax(carry, s_red[q]);
+    __syncthreads();
+    return fmax(incl, carry);
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_chunks(const double* __restrict__ agg,
+                                                            int32_t num_tiles,
+                                                            double* __restrict__ chunk) {
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ double s_red[NW];
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x;
+    double m = -INFINITY, sb = 0.0;
+    if (b < num_tiles) {
+        const double2 v = reinterpret_cast<const double2*>(agg)[b];
+        m = v.x;
+        sb = v.y;
+    }
+    const double mc = block_max<NW>(m, s_red);
+    const double w = (m == -INFINITY) ? 0.0 : sb * exp(m - mc);
+    double sc;
+    block_excl_sum<NW>(w, s_red, &sc);
+    if (threadIdx.x == 0) reinterpret_cast<double2*>(chunk)[blockIdx.x] = make_double2(mc, sc);
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(const double* __restrict__ chunk,
+                                                         int32_t num_chunks, int64_t n,
+                                                         double* __restrict__ pref, Totals* tot,
+                                                         DevState* st) {
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ double s_red[NW];
+    const int tid = threadIdx.x;
+    const int G = num_chunks;
+    const int per = (G + kScanBlock - 1) / kScanBlock;
+    const int g0 = min(G, tid * per), g1 = min(G, g0 + per);
+    double mx = -INFINITY;
+    for (int g = g0; g < g1; ++g) mx = fmax(mx, chunk[2 * g]);
+    const double M = block_max<NW>(mx, s_red);
+    auto weight = [&](int g) {
+        const double mg = chunk[2 * g];
+        return (mg == -INFINITY || M == -INFINITY) ? 0.0 : chunk[2 * g + 1] * exp(mg - M);
+    };
+    double part = 0.0;
+    for (int g = g0; g < g1; ++g) part += weight(g);
+    double total;
+    const double excl = block_excl_sum<NW>(part, s_red, &total);
+    // this thread's prefixes, made non-decreasing by the largest end of the
+    // threads before it
+    double run = excl;
+    for (int g = g0; g < g1; ++g) run += weight(g);
+    const double carry = block_excl_max<NW>(run, s_red);
+    run = excl;
+    for (int g = g0; g < g1; ++g) {
+        pref[g] = fmax(run, carry);
+        run += weight(g);
+    }
+    const double S = block_max<NW>(fmax(run, carry), s_red);
+    if (tid == 0) {
+        pref[G] = S;
+        const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
+        tot->M = M;
+        tot->S = S;
+        if (!ok) atomicOr(&st->flags, kDegenerate);
+        st->loglik += M + log(S / static_cast<double>(n));
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const double* __restrict__ agg,
+                                                           int32_t num_tiles, int64_t n,
+                                                           int32_t ts,
+                                                           const double* __restrict__ pref,
+                                                           const Totals* __restrict__ tot,
+                                                           TileAB* __restrict__ ab,
+                                                           int32_t* __restrict__ hint) {
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ double s_red[NW];
+    __shared__ double s_a[kScanBlock];
+    const int tid = threadIdx.x;
+    const int T = num_tiles;
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kScanBlock + tid;
+    const double M = tot->M, S = tot->S;
+    const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
+    const double lo = pref[blockIdx.x], hi = pref[blockIdx.x + 1];
+    double m = -INFINITY, sb = 0.0;
+    if (b < T) {
+        const double2 v = reinterpret_cast<const double2*>(agg)[b];
+        m = v.x;
+        sb = v.y;
+    }
+    const double e = (m == -INFINITY || M == -INFINITY) ? 0.0 : exp(m - M);
+    double unused;
+    const double x = lo + block_excl_sum<NW>(sb * e, s_red, &unused);
+    const double a = block_incl_max<NW>(ok ? fmin(x, hi) / S : 0.0, s_red);
+    if (b < T) ab[b] = TileAB{a, ok ? e / S : 0.0};
+    // hints: tile b owns output tiles ceil(A_b n / ts) <= h < ceil(A_{b+1} n / ts);
+    // tile 0 starts at h = 0 and the last tile runs to h = T.  The next
+    // chunk's first A equals min(P_{c+1}, P_{c+2}) / S = P_{c+1} / S.
+    s_a[tid] = a;
+    __syncthreads();
+    if (b >= T) return;
+    const double scale = static_cast<double>(n) / static_cast<double>(ts);
+    auto first_h = [&](int64_t bb, double abb) -> int64_t {
+        if (bb == 0) return 0;
+        if (bb >= T) return static_cast<int64_t>(T) + 1;
+        const double v = ceil(abb * scale);
+        return v > static_cast<double>(T) ? static_cast<int64_t>(T) : static_cast<int64_t>(v);
+    };
+    const double a_next = (tid + 1 < kScanBlock) ? s_a[tid + 1] : (ok ? hi / S : 0.0);
+    const int64_t h0 = first_h(b, a), h1 = first_h(b + 1, a_next);
+    for (int64_t h = h0; h < h1; ++h) hint[h] = static_cast<int32_t>(b);
 }
 
 // The batch's scans: work-group g scans filters g, g + grid, ... (those that
@@ -1235,10 +1419,31 @@ int batch_grid(int model, bool fp64, int ipt) {
     return cus * per;
 }
 
-hipError_t launch_scan_tiles(const double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
-                             int32_t* hint, Totals* tot, DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, s, agg, num_tiles, n, ts, ab, hint,
-                       tot, st);
+// Tile counts up to this use the single-work-group scan; above, the chunked
+// three-launch scan (chunk buffer: 2 doubles per chunk + G + 1 prefixes).
+constexpr int32_t kScanSingleMax = 4096;
+
+int32_t scan_chunks(int32_t num_tiles) {
+    return num_tiles <= kScanSingleMax ? 0 : (num_tiles + kScanBlock - 1) / kScanBlock;
+}
+
+hipError_t launch_scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
+                             int32_t* hint, Totals* tot, DevState* st, double* chunk,
+                             hipStream_t s) {
+    const int32_t G = scan_chunks(num_tiles);
+    if (G == 0) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, s, agg, num_tiles, n, ts,
+                           ab, hint, tot, st);
+        return hipGetLastError();
+    }
+    double* pref = chunk + 2 * static_cast<int64_t>(G);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(G), dim3(kScanBlock), 0, s,
+                       static_cast<const double*>(agg), num_tiles, chunk);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s,
+                       static_cast<const double*>(chunk), G, n, pref, tot, st);
+    hipLaunchKernelGGL(k_scan_apply, dim3(G), dim3(kScanBlock), 0, s,
+                       static_cast<const double*>(agg), num_tiles, n, ts,
+                       static_cast<const double*>(pref), static_cast<const Totals*>(tot), ab, hint);
     return hipGetLastError();
 }
 

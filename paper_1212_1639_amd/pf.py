@@ -28,7 +28,8 @@ MODEL_NAMES = {"ll_pf": LL_PF, "ll_pl": LL_PL, "sv_pf": SV_PF, "sv_pl": SV_PL}
 # every symbol include/pf.h declares
 EXPORTS = ["pf_fields", "pf_workspace_bytes", "pf_create", "pf_step", "pf_loglik", "pf_moments",
            "pf_destroy", "pf_last_error", "pf_batch_create", "pf_batch_update", "pf_batch_step",
-           "pf_batch_destroy", "pf_step_batch", "pf_debug_search", "pf_debug_particles"]
+           "pf_batch_destroy", "pf_step_batch", "pf_debug_search", "pf_debug_particles",
+           "pf_timing_start", "pf_timing_read", "pf_autotune", "pf_autotune_batch"]
 
 
 class PFError(RuntimeError):
@@ -94,6 +95,10 @@ def lib():
         L.pf_batch_step.argtypes = [vp, ctypes.POINTER(d), i64]
         L.pf_batch_destroy.argtypes = [vp]
         L.pf_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(d)]
+        L.pf_timing_start.argtypes = [vp, i64]
+        L.pf_autotune.argtypes = [cfgp, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
+        L.pf_autotune_batch.argtypes = [cfgp, i32, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
+        L.pf_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64)]
         for name in ("pf_create", "pf_step", "pf_loglik", "pf_moments", "pf_destroy",
                      "pf_batch_create", "pf_batch_update", "pf_batch_step", "pf_batch_destroy",
                      "pf_step_batch",
@@ -134,6 +139,34 @@ def workspace_bytes(cfg):
     if n == 0:
         raise PFError(EINVAL, lib().pf_last_error().decode())
     return n
+
+
+def autotune(cfg, y, stream=None):
+    """Tune cfg's items_per_thread, strategy and scan flag in place by timing
+    candidates over the host observations y; returns ms per step of the
+    winner."""
+    y = np.ascontiguousarray(y, dtype=np.float64).ravel()
+    ms = ctypes.c_double()
+    _check(lib().pf_autotune(ctypes.byref(cfg), y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             y.size, _stream_ptr(stream), ctypes.byref(ms)))
+    return ms.value
+
+
+def autotune_batch(cfgs, y, stream=None):
+    """Tune the common items_per_thread and strategy of filters stepped as one
+    batch; y is (n_obs, n_filters).  Updates cfgs in place; returns ms per
+    step of the winner."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n = len(cfgs)
+    assert y.ndim == 2 and y.shape[1] == n
+    arr = (Config * n)(*cfgs)
+    ms = ctypes.c_double()
+    _check(lib().pf_autotune_batch(arr, n, y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   y.shape[0], _stream_ptr(stream), ctypes.byref(ms)))
+    for k in range(n):
+        cfgs[k].items_per_thread = arr[k].items_per_thread
+        cfgs[k].strategy = arr[k].strategy
+    return ms.value
 
 
 def _stream_ptr(stream):
@@ -183,6 +216,17 @@ class Filter:
         rec = buf[:rec_bytes].view(dt).reshape(F, n).copy()
         anc = buf[rec_bytes:].view(np.int32).copy()
         return rec, anc, t.value
+
+    def timing_start(self, max_launches):
+        """Bracket the next `max_launches` cycle-kernel launches with events."""
+        _check(lib().pf_timing_start(self._h, int(max_launches)))
+
+    def timing_read(self):
+        """(summed milliseconds, launches) of the bracketed cycle kernels."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int64()
+        _check(lib().pf_timing_read(self._h, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
 
     def close(self):
         if self._h:

@@ -202,3 +202,26 @@ def test_run_from_a_state_continues_the_same_streams(orc, model):
     np.testing.assert_array_equal(part["anc"], full["anc"][t0:])
     np.testing.assert_array_equal(part["state"], full["state"][t0:])
     np.testing.assert_array_equal(part["loglik"], full["loglik"][t0:])
+
+
+@pytest.mark.parametrize("model,scheme", [("ll_pf", 1), ("ll_pl", 1), ("sv_pf", 2),
+                                          ("sv_pl", 2), ("ll_pl", 0), ("sv_pl", 0)])
+def test_sampled_step_equals_the_full_step(orc, model, scheme):
+    # the sampled step (used to check outputs at full sizes) computes the
+    # same ancestors and fields as the full step at the sampled slots
+    from tests import _cases as C
+    n, t0 = 1500, 4
+    cfg = C.oracle_config(orc, model, n, 5, ["multinomial", "stratified", "systematic"][scheme],
+                          fp32=True)
+    y = C.data(model, t0 + 1, seed=2)
+    ref = orc.run(cfg, y, dump=True)
+    st = ref["state"][t0 - 1]
+    full = orc.run(cfg, y[t0:], dump=True, state0=st, t0=t0, y_prev=y[t0 - 1])
+    slots = np.array([0, 1, 77, 700, 1498, 1499, 3])
+    anc, sst = orc.step_slots(cfg, st, t0, y[t0 - 1], y[t0], slots)
+    np.testing.assert_array_equal(anc, full["anc"][0][slots])
+    np.testing.assert_array_equal(sst, full["state"][0][:, slots])
+    # from the prior state at t0 = 0 the bootstrap models keep each slot's particle
+    if model != "ll_pl":
+        anc0, _ = orc.step_slots(cfg, ref["state"][0], 0, 0.0, y[0], slots)
+        np.testing.assert_array_equal(anc0, slots)
