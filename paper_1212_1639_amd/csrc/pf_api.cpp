@@ -78,9 +78,9 @@ int model_moments(int32_t model) {
 
 int choose_ipt(const pf_config& c) {
     if (c.items_per_thread) return c.items_per_thread;
-    // measured on MI355X: 4 items per thread up to 2^22 particles, 8 above
-    if (c.n_particles <= (int64_t(1) << 22)) return 4;
-    return 8;
+    // measured on MI355X: 4 items per thread (with 5 resident work-groups
+    // per CU) beats 2 and 8 from 2^20 to 2^26 particles
+    return 4;
 }
 
 struct Layout {

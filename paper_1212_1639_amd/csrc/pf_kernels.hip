@@ -41,6 +41,37 @@ constexpr int kLookPer = 4;
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Pointers typed in the global address space.  A buffer pointer read from
+// device memory (a batch's per-filter arguments) is generic to the compiler,
+// which then emits flat accesses with 64-bit vector addresses; every buffer
+// of a filter is device global memory, so the cycle accesses them through
+// these types (global loads and stores with a scalar base).
+// (The host pass of the compiler only checks device code; it sees plain
+// types.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using G = __attribute__((address_space(1))) T;
+#else
+template <typename T>
+using G = T;
+#endif
+template <typename T>
+__device__ __forceinline__ G<T>* gp(T* p) {
+    return (G<T>*)p;
+}
+
+// A value the whole work-group holds (read back from LDS), marked as
+// wave-uniform so that addresses derived from it stay in scalar registers.
+__device__ __forceinline__ uint32_t uniform32(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint64_t u = static_cast<uint64_t>(v);
+    const uint64_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint64_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((hi << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -129,9 +160,9 @@ __device__ __forceinline__ bool get_agg(const uint64_t* p, uint32_t epoch, Agg& 
 // tile-scan table (ab != nullptr) or from the look-back's (max, sum) form.
 template <typename R>
 struct PrevCdf {
-    const R* c;
-    const TileInfo* tiles;
-    const TileAB* ab;
+    G<const R>* c;
+    G<const TileInfo>* tiles;
+    G<const TileAB>* ab;
     double M, S;
     int64_t n;
     int32_t ts;  // elements per tile
@@ -211,47 +242,37 @@ __device__ __forceinline__ int lds_lower_bound(const double* s_q, int cnt, doubl
     return lo;
 }
 
-// Stage q(w0 .. w0+cnt-1) in LDS and make it non-decreasing (running max
-// from `floor`): rounding of the tile-wise representation can make adjacent
-// values differ by an ulp in the wrong direction, and every in-LDS search
-// below assumes a monotone array.  Loads are coalesced; the running max is a
-// per-thread pass over a contiguous chunk plus a block scan of the chunk
-// maxima.  Ends with a barrier.
+// Stage q(w0 .. w0+cnt-1) in LDS, non-decreasing.  Inside a tile the stored
+// prefix is non-decreasing and q = A_b + c[k] B_b (one fma, B_b >= 0) keeps
+// that order; across tiles rounding of the affine constants can leave a
+// tile's first value an ulp below its predecessor's last, so every value is
+// raised to the largest last value of the window's earlier tiles (and to
+// `floor`, the previous window's top).  Loads are coalesced.  Ends with a
+// barrier.
 template <int BLOCK, typename R>
 __device__ void stage_window(const PrevCdf<R>& P, int64_t w0, int cnt, double floor, double* s_q,
-                             double* s_ta, double* s_tb, double* s_red) {
+                             double* s_ta, double* s_tb, double* s_last) {
     const int tid = threadIdx.x;
     const int64_t b0 = w0 / P.ts, b1 = (w0 + cnt - 1) / P.ts;
     const int nb = static_cast<int>(b1 - b0 + 1);
-    for (int k = tid; k < nb; k += BLOCK) P.tile_ab(b0 + k, s_ta[k], s_tb[k]);
+    for (int k = tid; k < nb; k += BLOCK) {
+        double ta, tb;
+        P.tile_ab(b0 + k, ta, tb);
+        s_ta[k] = ta;
+        s_tb[k] = tb;
+        // the tile's last element inside the window
+        const int64_t e = min(w0 + cnt - 1, (b0 + k + 1) * P.ts - 1);
+        s_last[k] = e >= P.n - 1 ? 1.0 : fma(static_cast<double>(P.c[e]), tb, ta);
+    }
     __syncthreads();
     for (int k = tid; k < cnt; k += BLOCK) {
         const int64_t g = w0 + k;
+        const int bb = static_cast<int>(g / P.ts - b0);
         double v = 1.0;
-        if (g < P.n - 1) {
-            const int bb = static_cast<int>(g / P.ts - b0);
-            v = fma(static_cast<double>(P.c[g]), s_tb[bb], s_ta[bb]);
-        }
-        s_q[k] = v;
-    }
-    __syncthreads();
-    const int per = (cnt + BLOCK - 1) / BLOCK;
-    const int k0 = tid * per;
-    const int k1 = min(cnt, k0 + per);
-    double run = -INFINITY;
-    for (int k = k0; k < k1; ++k) run = fmax(run, s_q[k]);
-    const int lane = lane_id(), wave = tid / kWave;
-    const double incl = wave_incl_max(run);
-    if (lane == kWave - 1) s_red[wave] = incl;
-    __syncthreads();
-    double carry = floor;
-    for (int w = 0; w < wave; ++w) carry = fmax(carry, s_red[w]);
-    double excl = __shfl_up(incl, 1, kWave);
-    if (lane == 0) excl = -INFINITY;
-    carry = fmax(carry, excl);
-    for (int k = k0; k < k1; ++k) {
-        carry = fmax(carry, s_q[k]);
-        s_q[k] = carry;
+        if (g < P.n - 1) v = fma(static_cast<double>(P.c[g]), s_tb[bb], s_ta[bb]);
+        double f = floor;
+        for (int q = 0; q < bb; ++q) f = fmax(f, s_last[q]);
+        s_q[k] = fmax(v, f);
     }
     __syncthreads();
 }
@@ -314,6 +335,7 @@ struct StepSmem {
     double q[WIN];           // staged CDF window; reused for the scan
     int cut[kCutMax];        // cut-point table (CDFs of up to kCutMax entries)
     double ta[8], tb[8];     // per-tile affine constants of the window
+    double last[8];          // each window tile's last value
     double red[NW * 16];     // reductions
     int64_t lo, hi;
     uint32_t tile;
@@ -351,8 +373,9 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
         else w[i] = {0u, 0u, 0u, 0u};
     }
     if (resample) {
-        PrevCdf<R> P{static_cast<const R*>(A.c_in), A.tiles_in,
-                     A.scan == kScanTiles ? A.ab_in : nullptr, A.tot_in->M, A.tot_in->S, n, TS};
+        const G<const Totals>* tot_in = gp(A.tot_in);
+        PrevCdf<R> P{gp(static_cast<const R*>(A.c_in)), gp(A.tiles_in),
+                     A.scan == kScanTiles ? gp(A.ab_in) : nullptr, tot_in->M, tot_in->S, n, TS};
         const bool ok = (P.S > 0.0) && isfinite(P.S) && isfinite(P.M);
         if (!ok) {
             if (tid == 0) atomicOr(&A.st->flags, kDegenerate);
@@ -372,7 +395,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
             const int strategy = A.strategy;
             if (n <= WIN && strategy != kBinary) {
                 // the whole CDF fits one LDS window
-                stage_window<BLOCK>(P, 0, static_cast<int>(n), -INFINITY, sm.q, sm.ta, sm.tb, sm.red);
+                stage_window<BLOCK>(P, 0, static_cast<int>(n), -INFINITY, sm.q, sm.ta, sm.tb, sm.last);
                 if (strategy == kCutpoint) build_cutpoints<BLOCK>(sm.q, static_cast<int>(n), sm.cut);
 #pragma unroll
                 for (int i = 0; i < IPT; ++i) {
@@ -405,10 +428,10 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                         // its segment samples bracket u to one segment
                         constexpr int SEG = TS / kSegments;
                         const int64_t tmax = A.num_tiles - 1;
-                        const int64_t h = min(max(int64_t(A.hint_in[tile + wave]), int64_t(0)), tmax);
+                        const int64_t h = min(max(int64_t(gp(A.hint_in)[tile + wave]), int64_t(0)), tmax);
                         double ta, tb;
                         P.tile_ab(h, ta, tb);
-                        const R* samp = static_cast<const R*>(A.samp_in);
+                        G<const R>* samp = gp(static_cast<const R*>(A.samp_in));
                         const double qs = fma(static_cast<double>(samp[h * kSegments + lane]), tb, ta);
                         const uint64_t mask = __ballot(qs >= us);
                         const int f = mask ? __ffsll(static_cast<long long>(mask)) - 1 : kSegments;
@@ -440,10 +463,11 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 double floor = -INFINITY;
                 for (int64_t w0 = a_lo; w0 <= a_hi; w0 += WIN) {
                     const int cnt = static_cast<int>(min(static_cast<int64_t>(WIN), a_hi - w0 + 1));
-                    stage_window<BLOCK>(P, w0, cnt, floor, sm.q, sm.ta, sm.tb, sm.red);
+                    stage_window<BLOCK>(P, w0, cnt, floor, sm.q, sm.ta, sm.tb, sm.last);
                     const bool last = (w0 + cnt - 1 == a_hi);
                     const double top = sm.q[cnt - 1];
                     const bool first = (w0 == a_lo);
+
 #pragma unroll
                     for (int i = 0; i < IPT; ++i) {
                         if ((pending >> i) & 1u) {
@@ -481,8 +505,9 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
 
     // ---------------------------------------------------------- 2. propagate
     const ModelParams& p = A.p;
-    const R* rin = static_cast<const R*>(A.rec_in);
-    R* rout = static_cast<R*>(A.rec_out);
+    G<const R>* rin = gp(static_cast<const R*>(A.rec_in));
+    G<R>* rout = gp(static_cast<R*>(A.rec_out));
+    G<int32_t>* anc_out = A.anc_out ? gp(A.anc_out) : nullptr;
     R lw[IPT];
     // moment partials in the weights' precision: weighted ones relative to
     // the thread's running max (rescaled when it grows), equal-weight ones
@@ -514,7 +539,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 MD::template terms<R>(p, A.t, zn, g);
             }
             if (weight) lw[i] = MD::template logw<R>(p, zn, A.y_weight);
-            if (A.anc_out) A.anc_out[j] = anc[i];
+            if (anc_out) anc_out[j] = anc[i];
             if (weighted_mom) {
                 const R l = lw[i];
                 if (l > pm) {
@@ -572,7 +597,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 for (int k = 0; k < NG; ++k) out[3 + k] += r[3 + k] * f;
             }
             out[0] = weighted_mom ? Mx : 0.0;
-            double* dst = A.partials + static_cast<int64_t>(tile) * kPartialStride;
+            G<double>* dst = gp(A.partials) + static_cast<int64_t>(tile) * kPartialStride;
             for (int k = 0; k < 3 + NG; ++k) dst[k] = out[k];
         }
         __syncthreads();
@@ -589,7 +614,10 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     __syncthreads();
     double mb = -INFINITY;
     for (int q = 0; q < NW; ++q) mb = fmax(mb, sm.red[q]);
-    // e_k = exp(l_k - m_b) in the weights' precision, staged in slot order
+    // e_k = exp(l_k - m_b) in the weights' precision, staged in slot order.
+    // The blocked scan below has each thread read IPT consecutive slots; one
+    // pad entry per IPT slots keeps those reads off a common LDS bank.
+    auto pad = [](int slot) { return slot + slot / IPT; };
     const R mbr = static_cast<R>(mb);
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
@@ -597,7 +625,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
         const double e = (l == R(-INFINITY) || mb == -INFINITY)
                              ? 0.0
                              : static_cast<double>(Math<R>::exp(l - mbr));
-        sm.q[i * BLOCK + tid] = e;
+        sm.q[pad(i * BLOCK + tid)] = e;
     }
     __syncthreads();
     // blocked scan: thread owns IPT consecutive slots
@@ -605,7 +633,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     double run = 0.0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        run += sm.q[tid * IPT + i];
+        run += sm.q[tid * (IPT + 1) + i];
         v[i] = run;
     }
     const double tincl = wave_incl_sum(run);
@@ -618,13 +646,27 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     double texcl = __shfl_up(tincl, 1, kWave);
     if (lane == 0) texcl = 0.0;
     base += texcl;
+    // the threads' bases and runs are rounded separately, so a thread's first
+    // prefix can fall an ulp below its predecessor's last: raise each value to
+    // the largest last value of the threads before it (stored prefixes are
+    // then non-decreasing in the tile)
+    const double tlast = base + v[IPT - 1];
+    const double wmax = wave_incl_max(tlast);
+    if (lane == kWave - 1) sm.red[2 * NW + wave] = wmax;
+    __syncthreads();
+    double carry = -INFINITY;
+    for (int q = 0; q < wave; ++q) carry = fmax(carry, sm.red[2 * NW + q]);
+    double wex = __shfl_up(wmax, 1, kWave);
+    if (lane == 0) wex = -INFINITY;
+    carry = fmax(carry, wex);
     // back to slot order through LDS, so that the stores are coalesced;
     // single precision rounds toward zero so that a tile's last prefix never
     // exceeds the tile total the scan uses
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const double cval = base + v[i];
-        sm.q[tid * IPT + i] = sizeof(R) == 4 ? static_cast<double>(__double2float_rz(cval)) : cval;
+        const double cval = fmax(base + v[i], carry);
+        sm.q[tid * (IPT + 1) + i] =
+            sizeof(R) == 4 ? static_cast<double>(__double2float_rz(cval)) : cval;
     }
     __syncthreads();
     if (!lookback && tid < kSegments) {
@@ -633,22 +675,23 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
         constexpr int SEG = TS / kSegments;
         int64_t pos = static_cast<int64_t>(tid + 1) * SEG - 1;
         if (j0 + pos > n - 1) pos = n - 1 - j0;
-        static_cast<R*>(A.samp_out)[static_cast<int64_t>(tile) * kSegments + tid] =
-            static_cast<R>(sm.q[pos]);
+        gp(static_cast<R*>(A.samp_out))[static_cast<int64_t>(tile) * kSegments + tid] =
+            static_cast<R>(sm.q[pad(static_cast<int>(pos))]);
     }
-    R* cout = static_cast<R*>(A.c_out);
+    G<R>* cout = gp(static_cast<R*>(A.c_out));
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-        if (j < n) cout[j] = static_cast<R>(sm.q[i * BLOCK + tid]);
+        if (j < n) cout[j] = static_cast<R>(sm.q[pad(i * BLOCK + tid)]);
     }
     const Agg mine{mb, mb == -INFINITY ? 0.0 : total};
 
     if (!lookback) {
         // tile scan: publish the tile's (max, sum); k_scan_tiles does the rest
         if (tid == 0) {
-            A.agg_out[2 * static_cast<int64_t>(tile)] = mine.m;
-            A.agg_out[2 * static_cast<int64_t>(tile) + 1] = mine.s;
+            G<double>* agg = gp(A.agg_out);
+            agg[2 * static_cast<int64_t>(tile)] = mine.m;
+            agg[2 * static_cast<int64_t>(tile) + 1] = mine.s;
         }
         return;
     }
@@ -712,8 +755,19 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
 // One filter, one cycle: a work-group per tile.  With the look-back, tiles
 // are taken from a dynamic ticket, so that every tile a look-back waits on
 // was handed out earlier and is resident or done.
+// Work-groups per CU the register allocation is held to: the cycle is
+// latency-bound (dependent global loads for the search bracket, the window
+// and the gathers), so more resident waves pay for a few spilled registers.
+// With 8 items per thread the LDS window already limits residency to three.
+template <int IPT>
+constexpr int step_min_blocks() { return IPT >= 8 ? 3 : 5; }
+// The batched kernel carries the per-filter arguments in registers as well;
+// four resident work-groups per CU measured best for it.
+template <int IPT>
+constexpr int batch_min_blocks() { return IPT >= 8 ? 3 : 4; }
+
 template <int MODEL, typename R, int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
+__global__ __launch_bounds__(BLOCK, step_min_blocks<IPT>()) void k_step(StepArgs A) {
     __shared__ StepSmem<BLOCK, IPT> sm;
     uint32_t tile = blockIdx.x;
     if ((A.flags & kWeight) && A.scan == kScanLookback) {
@@ -721,7 +775,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
             sm.tile = __hip_atomic_fetch_add(&A.st->ticket, 1u, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        tile = sm.tile;
+        tile = uniform32(sm.tile);
     }
     cycle<MODEL, R, BLOCK, IPT>(A, tile, sm);
 }
@@ -734,21 +788,27 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
 // k_scan_batch), so the same pair of launches can be replayed step after
 // step.
 template <int MODEL, typename R, int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK) void k_step_batch(const StepArgs* __restrict__ descs,
+__global__ __launch_bounds__(BLOCK, batch_min_blocks<IPT>()) void k_step_batch(
+    const StepArgs* __restrict__ descs,
                                                       const int32_t* __restrict__ base,
                                                       BatchState* bs) {
     __shared__ StepSmem<BLOCK, IPT> sm;
-    const uint64_t step = __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int32_t n_filters = bs->n_filters;
+    // the batch's state is the same for the whole grid: keep it (and every
+    // address derived from it) in scalar registers
+    const uint64_t step = static_cast<uint64_t>(uniform64(static_cast<int64_t>(
+        __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))));
+    const int32_t n_filters = static_cast<int32_t>(uniform32(static_cast<uint32_t>(bs->n_filters)));
     if (n_filters <= 0) return;
     const int64_t total = base[n_filters];
-    const StepArgs* d = descs + (step % static_cast<uint64_t>(bs->ring)) * bs->capacity;
+    const uint32_t ring = uniform32(bs->ring);
+    const uint32_t capacity = uniform32(static_cast<uint32_t>(bs->capacity));
+    const StepArgs* d = descs + (step % ring) * capacity;
     while (true) {
         if (threadIdx.x == 0)
             sm.lo = static_cast<int64_t>(__hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT));
         __syncthreads();
-        const int64_t g = sm.lo;
+        const int64_t g = uniform64(sm.lo);
         __syncthreads();
         if (g >= total) break;
         // owner of global tile g: largest f with base[f] <= g
