@@ -144,25 +144,34 @@ def test_fp32_one_step_from_common_state(pf, orc, model, scheme):
 
 @pytest.mark.parametrize("model,scheme", FP32_MODELS)
 def test_fp32_trajectory(pf, orc, model, scheme):
-    """A whole single-precision run against the double-precision oracle:
-    |d loglik| <= 1e-3 T.  The filtered moments of the two runs decorrelate
-    after the first ancestor flips, so they are held to Monte Carlo
-    consistency: within 5% of the filtered standard deviation, several Monte
-    Carlo standard errors of a 2^16-particle filter."""
-    n, T = 1 << 16, 100
-    print(f"fp32 trajectory {model} n={n} {scheme} T={T}", flush=True)
+    """Whole single-precision runs against the double-precision oracle:
+    |d loglik| <= 1e-3 T.  A single-precision run and the oracle's run
+    decorrelate after their first ancestor flips, so one pair differs by
+    Monte Carlo noise (s.d. about 0.02-0.05 at N = 2^16, T = 100, i.e. the
+    bound is only about two standard deviations); the arithmetic's effect is
+    therefore measured on the means over 8 seeds (standard error about
+    0.015).  The filtered means are held to 5% of the filtered standard
+    deviation, again on the seed means."""
+    n, T, seeds = 1 << 16, 100, range(3, 11)
+    print(f"fp32 trajectory {model} n={n} {scheme} T={T} seeds={list(seeds)}", flush=True)
     y = C.data(model, T)
-    ref = orc.run(C.oracle_config(orc, model, n, 3, scheme, fp32=True), y)
-    f = pf.Filter(C.pf_config(pf, model, n, 3, scheme, fp32=True))
-    f.step(y)
-    ll = f.loglik()
-    mom = f.moments()
-    f.close()
-    assert abs(ll - ref["loglik"].sum()) <= 1e-3 * T, (ll, ref["loglik"].sum())
-    want = ref["moments"][-1, : mom.size]
-    sd = np.sqrt(want[1])
-    print("loglik", ll, ref["loglik"].sum(), "moments", mom, want)
-    assert abs(mom[0] - want[0]) <= 0.05 * sd
+    ll_gpu, ll_or, m_gpu, m_or, sd = [], [], [], [], []
+    for seed in seeds:
+        ref = orc.run(C.oracle_config(orc, model, n, seed, scheme, fp32=True), y)
+        f = pf.Filter(C.pf_config(pf, model, n, seed, scheme, fp32=True, keep_ancestors=False))
+        f.step(y)
+        ll_gpu.append(f.loglik())
+        mom = f.moments()
+        f.close()
+        ll_or.append(ref["loglik"].sum())
+        m_gpu.append(mom[0])
+        m_or.append(ref["moments"][-1, 0])
+        sd.append(np.sqrt(ref["moments"][-1, 1]))
+    d_ll = np.mean(ll_gpu) - np.mean(ll_or)
+    d_m = np.mean(m_gpu) - np.mean(m_or)
+    print("loglik means", np.mean(ll_gpu), np.mean(ll_or), "per seed", np.subtract(ll_gpu, ll_or))
+    assert abs(d_ll) <= 1e-3 * T, (d_ll, ll_gpu, ll_or)
+    assert abs(d_m) <= 0.05 * np.mean(sd), (d_m, m_gpu, m_or)
 
 
 def test_ll_pl_call_pattern_does_not_change_results(pf):
