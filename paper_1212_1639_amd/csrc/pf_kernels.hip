@@ -835,8 +835,122 @@ __global__ __launch_bounds__(BLOCK, batch_min_blocks<IPT>()) void k_step_batch(
 // tiles' maxima are overwritten (agg[2b] becomes e^{m_b - M}).
 constexpr int kScanBlock = 1024;
 
+// Up to kScanBlock * kScanPer tiles, each thread keeps its (at most
+// kScanPer) tiles in registers: one pass reads the (max, sum) pairs, one
+// writes the table and the hints, three barriers.
+constexpr int kScanPer = 4;
+
+__device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_tiles, int64_t n,
+                                                int32_t ts, TileAB* ab, int32_t* hint,
+                                                Totals* tot, DevState* st) {
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ double s_red[NW], s_first[kScanBlock];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int T = num_tiles;
+    const int per = (T + kScanBlock - 1) / kScanBlock;
+    const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
+    double m[kScanPer], w[kScanPer], e[kScanPer];
+    // 1. M = max_b m_b
+    double mx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        m[k] = -INFINITY;
+        w[k] = 0.0;
+        if (b0 + k < b1) {
+            const double2 v = reinterpret_cast<const double2*>(agg)[b0 + k];
+            m[k] = v.x;
+            w[k] = v.y;
+        }
+        mx = fmax(mx, m[k]);
+    }
+    mx = wave_max(mx);
+    if (lane == 0) s_red[wave] = mx;
+    __syncthreads();
+    double M = -INFINITY;
+    for (int q = 0; q < NW; ++q) M = fmax(M, s_red[q]);
+    __syncthreads();
+    // 2. e_b = e^{m_b - M}, w_b = s_b e_b; exclusive scan of the threads' sums
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        e[k] = (m[k] == -INFINITY || M == -INFINITY) ? 0.0 : exp(m[k] - M);
+        w[k] *= e[k];
+        part += w[k];
+    }
+    const double incl = wave_incl_sum(part);
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    double wbase = 0.0, S = 0.0;
+    for (int q = 0; q < NW; ++q) {
+        if (q == wave) wbase = S;
+        S += s_red[q];
+    }
+    double excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = 0.0;
+    excl += wbase;
+    const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
+    // 3. A_b, running max in the thread, then over the threads before it
+    double a[kScanPer];
+    double run = excl, amax = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        amax = fmax(amax, ok ? run / S : 0.0);
+        a[k] = amax;
+        run += w[k];
+    }
+    if (b0 >= b1) amax = -INFINITY;
+    s_first[tid] = b0 < b1 ? a[0] : -INFINITY;
+    __syncthreads();  // s_red is read above, by every thread, before this
+    const double top = wave_incl_max(amax);
+    if (lane == kWave - 1) s_red[wave] = top;
+    __syncthreads();
+    double carry = -INFINITY;
+    for (int q = 0; q < wave; ++q) carry = fmax(carry, s_red[q]);
+    double ex = __shfl_up(top, 1, kWave);
+    if (lane == 0) ex = -INFINITY;
+    carry = fmax(carry, ex);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        a[k] = fmax(a[k], carry);
+        if (b0 + k < b1) ab[b0 + k] = TileAB{a[k], ok ? e[k] / S : 0.0};
+    }
+    // 4. hints: tile b owns the output tiles h with ceil(A_b n / ts) <= h <
+    //    ceil(A_{b+1} n / ts); tile 0 starts at h = 0, the last tile runs to
+    //    h = T.  The next thread's first A (after its own carry, which is
+    //    this thread's carry raised by this thread's last value) closes the
+    //    thread's last range.
+    if (b0 >= b1) return;
+    const double scale = static_cast<double>(n) / static_cast<double>(ts);
+    auto first_h = [&](int b, double ab_a) -> int64_t {
+        if (b == 0) return 0;
+        if (b >= T) return static_cast<int64_t>(T) + 1;
+        const double v = ceil(ab_a * scale);
+        return v > static_cast<double>(T) ? static_cast<int64_t>(T) : static_cast<int64_t>(v);
+    };
+    const double next_a = b1 < T ? fmax(s_first[tid + 1], fmax(carry, amax)) : 0.0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int b = b0 + k;
+        if (b < b1) {
+            const double an = (b + 1 < b1) ? a[k + 1 < kScanPer ? k + 1 : k] : next_a;
+            const int64_t h0 = first_h(b, a[k]), h1 = first_h(b + 1, an);
+            for (int64_t h = h0; h < h1; ++h) hint[h] = b;
+        }
+    }
+    if (tid == 0) {
+        tot->M = M;
+        tot->S = S;
+        if (!ok) atomicOr(&st->flags, kDegenerate);
+        st->loglik += M + log(S / static_cast<double>(n));
+    }
+}
+
 __device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts,
                                            TileAB* ab, int32_t* hint, Totals* tot, DevState* st) {
+    if (num_tiles <= kScanBlock * kScanPer) {
+        scan_tiles_regs(agg, num_tiles, n, ts, ab, hint, tot, st);
+        return;
+    }
     constexpr int NW = kScanBlock / kWave;
     __shared__ double s_red[NW], s_top[NW];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
