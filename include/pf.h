@@ -276,15 +276,17 @@ int pf_autotune_batch(pf_config* cfgs, int32_t n, const double* y, int64_t n_obs
 
 /* Kernel timing, a measurement aid (not part of the method).
  * pf_timing_start synchronises f's stream and arms max_launches
- * (1 <= max_launches <= 2^20) pairs of HIP events: each of f's next
- * cycle-kernel launches, up to that many, is bracketed by one pair on f's
- * stream (the CDF tile scan that follows a weighting launch is outside the
- * bracket).  pf_timing_read synchronises, returns in *total_ms the summed
- * event-to-event time of the bracketed launches and in *launches their
- * count, and disarms.  Arming again discards earlier pairs.  The events are
- * owned by the handle and released by pf_timing_read or pf_destroy.
- * Errors: PF_EINVAL (null argument, bad count), PF_EDEVICE. */
-int pf_timing_start(pf_filter* f, int64_t max_launches);
+ * (1 <= max_launches <= 2^20) pairs of HIP events: of f's next cycle-kernel
+ * launches, the 1st, (every+1)-th, (2 every+1)-th, ... (every >= 1), up to
+ * max_launches of them, are each bracketed by one pair on f's stream (the
+ * CDF tile scan that follows a weighting launch is outside the bracket);
+ * bracketing one launch in `every` keeps the events' own cost out of the
+ * other launches.  pf_timing_read synchronises, returns in *total_ms the
+ * summed event-to-event time of the bracketed launches and in *launches
+ * their count, and disarms.  Arming again discards earlier pairs.  The
+ * events are owned by the handle and released by pf_timing_read or
+ * pf_destroy.  Errors: PF_EINVAL (null argument, bad count), PF_EDEVICE. */
+int pf_timing_start(pf_filter* f, int64_t max_launches, int64_t every);
 int pf_timing_read(pf_filter* f, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus

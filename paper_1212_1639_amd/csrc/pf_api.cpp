@@ -233,7 +233,9 @@ struct pf_filter {
     pf::ModelParams mp;
     // kernel timing: event pairs bracketing the cycle-kernel launches
     std::vector<hipEvent_t> tev;
-    int64_t timed = 0;
+    int64_t timed = 0;       // bracketed launches so far
+    int64_t launches = 0;    // cycle launches since timing was armed
+    int64_t every = 1;       // bracket one launch in `every`
 
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -316,7 +318,8 @@ struct pf_filter {
     }
 
     int run(const pf::StepArgs& a) {
-        const bool timing = 2 * timed + 1 < static_cast<int64_t>(tev.size());
+        const bool timing = 2 * timed + 1 < static_cast<int64_t>(tev.size()) &&
+                            launches++ % every == 0;
         if (timing && hipEventRecord(tev[2 * timed], stream) != hipSuccess)
             return hip_fail(hipGetLastError(), "timing event");
         hipError_t e = pf::launch_step(cfg.model, cfg.precision == PF_FP64, L.ipt, a, L.num_tiles,
@@ -475,15 +478,19 @@ static void release_timing(pf_filter* f) {
     for (hipEvent_t ev : f->tev) hipEventDestroy(ev);
     f->tev.clear();
     f->timed = 0;
+    f->launches = 0;
+    f->every = 1;
 }
 
-int pf_timing_start(pf_filter* f, int64_t max_launches) {
+int pf_timing_start(pf_filter* f, int64_t max_launches, int64_t every) {
     if (!f) return fail(PF_EINVAL, "null filter");
     if (max_launches < 1 || max_launches > (1 << 20))
         return fail(PF_EINVAL, "max_launches must be in [1, 2^20]");
+    if (every < 1) return fail(PF_EINVAL, "every must be >= 1");
     hipError_t e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return hip_fail(e, "pf_timing_start synchronise");
     release_timing(f);
+    f->every = every;
     f->tev.resize(static_cast<size_t>(2 * max_launches));
     for (size_t i = 0; i < f->tev.size(); ++i) {
         e = hipEventCreate(&f->tev[i]);

@@ -95,7 +95,7 @@ def lib():
         L.pf_batch_step.argtypes = [vp, ctypes.POINTER(d), i64]
         L.pf_batch_destroy.argtypes = [vp]
         L.pf_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(d)]
-        L.pf_timing_start.argtypes = [vp, i64]
+        L.pf_timing_start.argtypes = [vp, i64, i64]
         L.pf_autotune.argtypes = [cfgp, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
         L.pf_autotune_batch.argtypes = [cfgp, i32, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
         L.pf_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64)]
@@ -217,9 +217,10 @@ class Filter:
         anc = buf[rec_bytes:].view(np.int32).copy()
         return rec, anc, t.value
 
-    def timing_start(self, max_launches):
-        """Bracket the next `max_launches` cycle-kernel launches with events."""
-        _check(lib().pf_timing_start(self._h, int(max_launches)))
+    def timing_start(self, max_launches, every=1):
+        """Bracket one in `every` of the next cycle-kernel launches with
+        events, at most `max_launches` of them."""
+        _check(lib().pf_timing_start(self._h, int(max_launches), int(every)))
 
     def timing_read(self):
         """(summed milliseconds, launches) of the bracketed cycle kernels."""

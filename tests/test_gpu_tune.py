@@ -103,6 +103,12 @@ def test_kernel_timing(pf):
     assert k == 20 and ms > 0
     ms2, k2 = f.timing_read()   # disarmed after a read
     assert k2 == 0 and ms2 == 0
+    f.timing_start(100, every=4)
+    f.step(y[:25])          # launches 0, 4, ..., 24
+    ms3, k3 = f.timing_read()
+    assert k3 == 7 and ms3 > 0
     with pytest.raises(pf.PFError):
         f.timing_start(0)
+    with pytest.raises(pf.PFError):
+        f.timing_start(10, every=0)
     f.close()
