@@ -22,6 +22,12 @@ Workloads (all synthetic; data simulated from the model):
               with continuous batching under a memory budget (80% of free
               device memory, or --serve-budget-gb); reports p50/p99 per-step
               latency and aggregate particle-steps/s
+  paper_table2  the paper's experiment (Section 4): particle learning on the
+              local-level model, IG(5, 4) / IG(5, 0.4) priors, T = 100,
+              multinomial, the particle record copied to host memory
+              after every cycle, N = 2^10 .. 2^23, single and double precision, 10 runs
+              per size (mean of the 5 closest to the median; --steps sets
+              the run count), plus the phase breakdown at 131,072
   ll_pl_batch256  256 independent local-level particle-learning filters, each
               with its own seed and data, N drawn log-uniform in [2^12, 2^18],
               T = 200, stratified, FP32; stepped together (one persistent
@@ -92,6 +98,13 @@ WORKLOADS = {
                        bytes_per_particle=2 * 8 + 16),
     "served_mix": dict(model="mix", n=None, T=None, scheme="mixed", fp32=True, served=True,
                        rate=200.0, duration=30.0, bytes_per_particle=None),
+    # the paper's experiment (Section 4, Tables 2 and 3): particle learning on
+    # the local-level model with IG(5, 4) and IG(5, 0.4) priors, T = 100, the
+    # particles stored to host memory every step, 10 runs per size
+    "paper_table2": dict(model="ll_pl", n=None, T=100, scheme="multinomial", fp32=True, paper=True,
+                         params=dict(x0_mean=0.0, x0_var=10.0, a_v=5.0, b_v=4.0, a_w=5.0, b_w=0.4),
+                         sizes=[1024, 4096, 16384, 131072, 1048576, 8388608], runs=10,
+                         bytes_per_particle=2 * 20 + 8),
     "ll_pl_batch256": dict(model="ll_pl", n=None, T=200, scheme="stratified", fp32=True,
                            filters=256, params=dict(x0_mean=0.0, x0_var=10.0, a_v=2.0, b_v=1.0,
                                                     a_w=2.0, b_w=1.0),
@@ -135,6 +148,109 @@ def run_served(args, w, pf, torch):
         "served": {k: st[k] for k in ("completed", "rejected", "ticks", "wall_s",
                                       "particle_steps", "step_latency_ms", "queue_delay_ms",
                                       "max_bytes_in_use")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+# The paper's GPU(sp) / GPU(dp) times in ms (Table 2; GTX 580) and the
+# breakdown at 131,072 particles (Table 3): context only, other hardware.
+PAPER_TABLE2_MS = {"sp": {1024: 17, 4096: 21, 16384: 51, 131072: 216, 1048576: 1527,
+                          8388608: 11878},
+                   "dp": {1024: 20, 4096: 25, 16384: 130, 131072: 429}}
+
+
+def _median5(xs):
+    """Mean of the five values closest to the median (the paper's protocol)."""
+    xs = np.asarray(xs, dtype=np.float64)
+    med = np.median(xs)
+    return float(np.mean(xs[np.argsort(np.abs(xs - med))[:5]]))
+
+
+def run_paper(args, w, pf, torch):
+    """The paper's experiment: whole particle-learning runs (initialise, T
+    cycles, the particles copied to host memory after every cycle), 10 runs
+    per size, mean of the 5 closest to the median; single and double
+    precision; and the phase breakdown at 131,072."""
+    from paper_1212_1639_amd import inputs
+    T = w["T"]
+    y = inputs.local_level(T, seed=0)[0]
+    stream = torch.cuda.Stream()
+    runs = args.steps or w["runs"]
+    sizes = [n for n in w["sizes"] if not args.paper_max_n or n <= args.paper_max_n]
+    table = {"sp": {}, "dp": {}}
+    for prec, key in ((pf.FP32, "sp"), (pf.FP64, "dp")):
+        for n in sizes:
+            def cfg(seed):
+                return pf.make_config(w["model"], n, seed, scheme=pf.MULTINOMIAL, precision=prec,
+                                      **w["params"])
+            times = []
+            for r in range(runs + 1):           # run 0 warms up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f = pf.Filter(cfg(r + 1), stream=stream)
+                for t in range(T):
+                    f.step(y[t])
+                    f.particles()               # store: record to host memory
+                torch.cuda.synchronize()
+                if r:
+                    times.append(time.perf_counter() - t0)
+                f.close()
+            table[key][n] = _median5(times) * 1e3 if len(times) >= 5 else float(np.mean(times)) * 1e3
+            print(f"paper_table2 {key} N={n}: {table[key][n]:.2f} ms", file=sys.stderr, flush=True)
+    # phase breakdown at 131,072 particles, single precision
+    n = 131072
+    breakdown = {}
+    if n in sizes:
+        c = pf.make_config(w["model"], n, 1, scheme=pf.MULTINOMIAL, precision=pf.FP32,
+                           **w["params"])
+        ph = {"initialize": [], "cycles": [], "cycles_and_store": []}
+        for r in range(runs + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = pf.Filter(c, stream=stream)
+            stream.synchronize()
+            t1 = time.perf_counter()
+            f.step(y)
+            stream.synchronize()
+            t2 = time.perf_counter()
+            f.close()
+            f = pf.Filter(c, stream=stream)
+            stream.synchronize()
+            t3 = time.perf_counter()
+            for t in range(T):
+                f.step(y[t])
+                f.particles()
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            f.close()
+            if r:
+                ph["initialize"].append(t1 - t0)
+                ph["cycles"].append(t2 - t1)
+                ph["cycles_and_store"].append(t4 - t3)
+        breakdown = {k: _median5(v) * 1e3 for k, v in ph.items()}
+        breakdown["store"] = breakdown["cycles_and_store"] - breakdown["cycles"]
+    nmax = max(table["sp"])
+    value = nmax * T / (table["sp"][nmax] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": T,
+        "warmup": 1,
+        "ms_per_step": table["sp"][nmax] / T,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "model": w["model"], "T": T, "scheme": "multinomial",
+                   "priors": "IG(5,4), IG(5,0.4)", "runs": runs, "form": "plain",
+                   "store": "particle record to host memory after every cycle (synchronous)"},
+        "table2_ms": {k: {str(n): round(v, 3) for n, v in d.items()} for k, d in table.items()},
+        "table3_131072_ms": {k: round(v, 3) for k, v in breakdown.items()},
+        "paper_gpu_ms_context": {k: {str(n): v for n, v in d.items()}
+                                 for k, d in PAPER_TABLE2_MS.items()},
     }
     print(json.dumps(out), flush=True)
 
@@ -283,6 +399,8 @@ def main():
                     help="served_mix: device memory budget (default 80%% of free memory)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="served_mix: length of the arrival window (default 30 s)")
+    ap.add_argument("--paper-max-n", type=int, default=0,
+                    help="paper_table2: largest N to run (default all, up to 2^23)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the filter, copy MIB mebibytes device to device (a plain "
                          "copy kernel of known size, to scale the profiler's byte counters)")
@@ -314,6 +432,10 @@ def main():
     if w.get("filters"):
         torch.cuda.set_device(0)
         run_batch(args, w, pf, torch)
+        return
+    if w.get("paper"):
+        torch.cuda.set_device(0)
+        run_paper(args, w, pf, torch)
         return
     K = args.steps or w["T"]
     W = args.warmup

@@ -245,6 +245,23 @@ int pf_debug_search(const double* cdf_dev, const double* u_dev, int64_t n, int64
  * (L00 = p0 + t and the shape a_s + t/2 are the same for every particle). */
 int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_out);
 
+/* Copy the current particles' record (pf_fields(model) arrays of N
+ * values, float for PF_FP32 and double for PF_FP64, as pf_debug_particles
+ * lays them out, without the ancestors) to host memory asynchronously: the
+ * copy is queued on copy_stream (a hipStream_t; NULL = the null stream)
+ * after f's latest launch, and f's next launch that would overwrite those
+ * particles (two propagations later: the record is double-buffered) first
+ * waits for the copy, so stepping continues while the copy runs.  host_dst
+ * (caller-owned, at least bytes >= fields * N * element size) should be
+ * pinned (hipHostMalloc) for the copy to be asynchronous; its contents are
+ * valid once copy_stream has passed the copy.  This is the "store the
+ * particles in host memory" phase of the paper's experiment (Section 4),
+ * overlapped with the next step.  Errors: PF_EINVAL, PF_EDEVICE.
+ * CURRENTLY SWITCHED OFF: the call returns PF_EDEVICE without doing anything
+ * (its first GPU run faulted; the cause is not yet found).  Use
+ * pf_debug_particles for a synchronous copy. */
+int pf_copy_particles_async(pf_filter* f, void* host_dst, size_t bytes, void* copy_stream);
+
 /* Autotuner (a runtime aid, not part of the method): picks the tile size
  * (cfg->items_per_thread), the search strategy (cfg->strategy) and the CDF
  * scan (the PF_FLAG_LOOKBACK_SCAN bit of cfg->flags) for cfg by timing

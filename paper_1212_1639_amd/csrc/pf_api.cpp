@@ -231,6 +231,23 @@ struct pf_filter {
     uint32_t epoch = 0;      // look-back tag of the latest weighting launch
     int32_t weighted_partials = 0;
     pf::ModelParams mp;
+    // asynchronous copies of a record buffer to the host: a launch that
+    // overwrites buffer b first waits for copy_ev[b]
+    hipEvent_t copy_ev[2] = {nullptr, nullptr};
+    bool copy_pending[2] = {false, false};
+    hipEvent_t step_ev = nullptr;
+
+    int wait_copy(hipStream_t s, int b) {
+        if (!copy_pending[b]) return PF_OK;
+        copy_pending[b] = false;
+        const hipError_t e = hipStreamWaitEvent(s, copy_ev[b], 0);
+        return e == hipSuccess ? PF_OK : hip_fail(e, "wait for a particle copy");
+    }
+    int wait_copies(hipStream_t s) {
+        int rc = wait_copy(s, 0);
+        return rc != PF_OK ? rc : wait_copy(s, 1);
+    }
+
     // kernel timing: event pairs bracketing the cycle-kernel launches
     std::vector<hipEvent_t> tev;
     int64_t timed = 0;       // bracketed launches so far
@@ -318,6 +335,11 @@ struct pf_filter {
     }
 
     int run(const pf::StepArgs& a) {
+        if (a.flags & pf::kPropagate) {
+            const int b = a.rec_out == static_cast<void*>(ws + L.rec[0]) ? 0 : 1;
+            const int rc = wait_copy(stream, b);
+            if (rc != PF_OK) return rc;
+        }
         const bool timing = 2 * timed + 1 < static_cast<int64_t>(tev.size()) &&
                             launches++ % every == 0;
         if (timing && hipEventRecord(tev[2 * timed], stream) != hipSuccess)
@@ -526,6 +548,15 @@ int pf_timing_read(pf_filter* f, double* total_ms, int64_t* launches) {
 int pf_destroy(pf_filter* f) {
     if (!f) return PF_OK;
     hipError_t e = hipStreamSynchronize(f->stream);
+    // the workspace may still be read by a particle copy on another stream
+    for (int b = 0; b < 2; ++b) {
+        if (f->copy_ev[b]) {
+            const hipError_t e2 = hipEventSynchronize(f->copy_ev[b]);
+            if (e == hipSuccess) e = e2;
+            hipEventDestroy(f->copy_ev[b]);
+        }
+    }
+    if (f->step_ev) hipEventDestroy(f->step_ev);
     release_timing(f);
     if (f->owns_ws) hipFree(f->ws);
     delete f;
@@ -588,6 +619,38 @@ int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_ou
     if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return hip_fail(e, "pf_debug_particles");
     if (t_out) *t_out = f->t;
+    return PF_OK;
+}
+
+// Switched off: the first GPU run of this path (a pitched device-to-host
+// copy into pinned memory on a second stream, ordered by events) ended in a
+// GPU memory fault whose cause has not been found; until it is, the call
+// refuses to run.
+constexpr bool kAsyncParticleCopies = false;
+
+int pf_copy_particles_async(pf_filter* f, void* host_dst, size_t bytes, void* copy_stream) {
+    if (!kAsyncParticleCopies)
+        return fail(PF_EDEVICE, "asynchronous particle copies are switched off in this build");
+    if (!f || !host_dst) return fail(PF_EINVAL, "null argument");
+    const size_t row = static_cast<size_t>(f->cfg.n_particles) * f->L.rsz;
+    const size_t need = row * static_cast<size_t>(f->L.fields);
+    if (bytes < need) return fail(PF_EINVAL, "host buffer smaller than the particle record");
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+        if (!f->copy_ev[b]) e = hipEventCreateWithFlags(&f->copy_ev[b], hipEventDisableTiming);
+    if (e == hipSuccess && !f->step_ev) e = hipEventCreateWithFlags(&f->step_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "pf_copy_particles_async event");
+    const hipStream_t cs = static_cast<hipStream_t>(copy_stream);
+    const int b = f->cur;
+    e = hipEventRecord(f->step_ev, f->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, f->step_ev, 0);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(host_dst, row, f->ws + f->L.rec[b],
+                             static_cast<size_t>(f->L.pitch) * f->L.rsz, row,
+                             static_cast<size_t>(f->L.fields), hipMemcpyDeviceToHost, cs);
+    if (e == hipSuccess) e = hipEventRecord(f->copy_ev[b], cs);
+    if (e != hipSuccess) return hip_fail(e, "pf_copy_particles_async");
+    f->copy_pending[b] = true;
     return PF_OK;
 }
 
@@ -708,6 +771,12 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
     const int64_t cap = b->capacity;
     for (int64_t i = 0; i < n * n_steps; ++i)
         if (!std::isfinite(y[i])) return fail(PF_EINVAL, "observation is not finite");
+    // members' particles still being copied to the host are overwritten by
+    // the batched steps: wait for those copies first
+    for (pf_filter* f : b->fs) {
+        const int rc = f->wait_copies(b->stream);
+        if (rc != PF_OK) return rc;
+    }
     hipError_t e = hipSuccess;
     if (!b->exec) {
         // capture one batched cycle (its arguments come from the device ring)

@@ -29,7 +29,8 @@ MODEL_NAMES = {"ll_pf": LL_PF, "ll_pl": LL_PL, "sv_pf": SV_PF, "sv_pl": SV_PL}
 EXPORTS = ["pf_fields", "pf_workspace_bytes", "pf_create", "pf_step", "pf_loglik", "pf_moments",
            "pf_destroy", "pf_last_error", "pf_batch_create", "pf_batch_update", "pf_batch_step",
            "pf_batch_destroy", "pf_step_batch", "pf_debug_search", "pf_debug_particles",
-           "pf_timing_start", "pf_timing_read", "pf_autotune", "pf_autotune_batch"]
+           "pf_timing_start", "pf_timing_read", "pf_autotune", "pf_autotune_batch",
+           "pf_copy_particles_async"]
 
 
 class PFError(RuntimeError):
@@ -96,6 +97,7 @@ def lib():
         L.pf_batch_destroy.argtypes = [vp]
         L.pf_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(d)]
         L.pf_timing_start.argtypes = [vp, i64, i64]
+        L.pf_copy_particles_async.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.pf_autotune.argtypes = [cfgp, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
         L.pf_autotune_batch.argtypes = [cfgp, i32, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
         L.pf_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64)]
@@ -216,6 +218,22 @@ class Filter:
         rec = buf[:rec_bytes].view(dt).reshape(F, n).copy()
         anc = buf[rec_bytes:].view(np.int32).copy()
         return rec, anc, t.value
+
+    def record_shape(self):
+        """(fields, N) and numpy dtype of the particle record."""
+        F = lib().pf_fields(self.cfg.model)
+        dt = np.float64 if self.cfg.precision == FP64 else np.float32
+        return (F, self.cfg.n_particles), dt
+
+    def copy_particles_async(self, host, copy_stream):
+        """Queue a copy of the current particle record into `host` (a pinned
+        CPU torch tensor of the record's shape and dtype) on `copy_stream`;
+        the filter keeps stepping while it runs."""
+        (F, n), dt = self.record_shape()
+        assert host.is_pinned() and not host.is_cuda and host.numel() * host.element_size() >= F * n * np.dtype(dt).itemsize
+        _check(lib().pf_copy_particles_async(self._h, ctypes.c_void_p(host.data_ptr()),
+                                             host.numel() * host.element_size(),
+                                             _stream_ptr(copy_stream)))
 
     def timing_start(self, max_launches, every=1):
         """Bracket one in `every` of the next cycle-kernel launches with
