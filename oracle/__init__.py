@@ -33,7 +33,7 @@ _SRC = os.path.join(_HERE, "pf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 LL_PF, LL_PL, SV_PF, SV_PL = 0, 1, 2, 3
-MULTINOMIAL, STRATIFIED, SYSTEMATIC = 0, 1, 2
+MULTINOMIAL, STRATIFIED, SYSTEMATIC, SORTED_MULTINOMIAL = 0, 1, 2, 3
 SEARCH_BINARY, SEARCH_CUTPOINT, SEARCH_BRUTE = 0, 1, 2
 NMOM = 8
 FIELDS = {LL_PF: 1, LL_PL: 5, SV_PF: 1, SV_PL: 7}

@@ -236,9 +236,23 @@ void or_resample(const double* q, int64_t n, const double* u, int64_t m, int met
  *   multinomial: u_j i.i.d. uniform, word 0 of ST_STEP at (j, t);
  *   stratified:  u_j = (j + U_j)/N with U_j from the same word;
  *   systematic:  u_j = (j + U)/N with the one U from word 0 of
- *                ST_SYSTEMATIC at (0, t).
+ *                ST_SYSTEMATIC at (0, t);
+ *   sorted multinomial: the order statistics of N i.i.d. uniforms, formed
+ *                without sorting from exponential spacings: with
+ *                E_i = -log U_i (U_i from word 0 of ST_STEP at (i, t),
+ *                i = 0..N) and P_j = E_0 + ... + E_j, u_j = P_j / P_N.
+ *                The ancestors' counts are multinomial exactly; the slots
+ *                receive them in increasing order.
  * j is 0-based, so stratum j is [j/N, (j+1)/N]. */
-enum { OR_MULTINOMIAL = 0, OR_STRATIFIED = 1, OR_SYSTEMATIC = 2 };
+enum { OR_MULTINOMIAL = 0, OR_STRATIFIED = 1, OR_SYSTEMATIC = 2, OR_SORTED_MULTINOMIAL = 3 };
+
+/* Exponential spacing E_i = -log U_i of index i at time t. */
+static double spacing(uint64_t seed, uint32_t t, int64_t i)
+{
+    uint32_t w[4];
+    words(seed, (uint32_t)i, t, ST_STEP, 0, w);
+    return -log(or_u32(w[0]));
+}
 
 /* Uniform u_j of slot j; U_sys is the systematic offset of time t. */
 static double slot_uniform(int scheme, uint64_t seed, uint32_t t, int64_t n, int64_t j,
@@ -261,6 +275,16 @@ static double systematic_offset(int scheme, uint64_t seed, uint32_t t)
 
 void or_uniforms(int scheme, uint64_t seed, uint32_t t, int64_t n, double* u)
 {
+    if (scheme == OR_SORTED_MULTINOMIAL) {
+        double P = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            P += spacing(seed, t, j);
+            u[j] = P;
+        }
+        const double PN = P + spacing(seed, t, n);
+        for (int64_t j = 0; j < n; ++j) u[j] /= PN;
+        return;
+    }
     const double U = systematic_offset(scheme, seed, t);
     for (int64_t j = 0; j < n; ++j) u[j] = slot_uniform(scheme, seed, t, n, j, U);
 }
@@ -878,8 +902,15 @@ int or_step_slots(const or_config* c, const double* state0, int64_t t0, double y
         double M, S;
         or_cdf(lw, N, q, &M, &S);
         if (!(S > 0.0) || !isfinite(S) || !isfinite(M)) rc = -1;
-        const double U = systematic_offset(c->scheme, c->seed, t);
-        for (int64_t i = 0; i < k; ++i) u[i] = slot_uniform(c->scheme, c->seed, t, N, slots[i], U);
+        if (c->scheme == OR_SORTED_MULTINOMIAL) {
+            double* all = (double*)malloc(sizeof(double) * N);
+            or_uniforms(c->scheme, c->seed, t, N, all);
+            for (int64_t i = 0; i < k; ++i) u[i] = all[slots[i]];
+            free(all);
+        } else {
+            const double U = systematic_offset(c->scheme, c->seed, t);
+            for (int64_t i = 0; i < k; ++i) u[i] = slot_uniform(c->scheme, c->seed, t, N, slots[i], U);
+        }
         or_resample(q, N, u, k, c->search, anc_out);
         free(lw); free(q); free(u);
     } else {

@@ -1,20 +1,23 @@
-"""Pins of the oracle's three resampling schemes (Section 3.1).
+"""Pins of the oracle's resampling schemes (Section 3.1; sorted multinomial
+from exponential spacings).
 
 Offspring invariants, the exact law of the ancestor vector at N <= 8 by
-enumeration, and unbiasedness E[offspring_i] = N w_i over many seeds.
+enumeration, unbiasedness E[offspring_i] = N w_i over many seeds, and the
+order-statistic law of the sorted multinomial uniforms.
 """
+import math
 import itertools
 
 import numpy as np
 import pytest
 from scipy import stats
 
-SCHEMES = ["multinomial", "stratified", "systematic"]
+SCHEMES = ["multinomial", "stratified", "systematic", "sorted_multinomial"]
 
 
 def _scheme(orc, name):
     return {"multinomial": orc.MULTINOMIAL, "stratified": orc.STRATIFIED,
-            "systematic": orc.SYSTEMATIC}[name]
+            "systematic": orc.SYSTEMATIC, "sorted_multinomial": orc.SORTED_MULTINOMIAL}[name]
 
 
 def _weights(n, seed):
@@ -60,6 +63,16 @@ def _exact_law(scheme, q):
     if scheme == "multinomial":
         w = np.diff(edges)
         return {v: float(np.prod(w[list(v)])) for v in itertools.product(range(n), repeat=n)}
+    if scheme == "sorted_multinomial":
+        # non-decreasing vectors only, each with the multinomial probability
+        # of its offspring counts
+        w = np.diff(edges)
+        law = {}
+        for v in itertools.combinations_with_replacement(range(n), n):
+            o = np.bincount(v, minlength=n)
+            coef = math.factorial(n) / np.prod([math.factorial(int(k)) for k in o])
+            law[v] = float(coef * np.prod(w ** o))
+        return law
     if scheme == "stratified":
         per = []
         for j in range(n):
@@ -137,3 +150,15 @@ def test_unbiased_offspring(orc, scheme):
     se = np.sqrt(n * w * (1 - w) / S) + 1e-12
     z = np.abs(mean - n * w) / se
     assert np.all(z < 4.5), (scheme, z.max())
+
+
+def test_sorted_multinomial_uniforms_are_order_statistics(orc):
+    # u_j is the (j+1)-th smallest of N i.i.d. uniforms: Beta(j + 1, N - j)
+    n, S = 12, 3000
+    us = np.array([orc.uniforms(orc.SORTED_MULTINOMIAL, seed, 2, n) for seed in range(S)])
+    assert np.all(np.diff(us, axis=1) > 0) and np.all(us > 0) and np.all(us < 1)
+    for j in (0, 5, 11):
+        assert stats.kstest(us[:, j], stats.beta(j + 1, n - j).cdf).pvalue > 1e-4
+    # the spacings' ratios are independent of the scale: gaps have the law of
+    # a uniform spacing, Beta(1, N)
+    assert stats.kstest(us[:, 7] - us[:, 6], stats.beta(1, n).cdf).pvalue > 1e-4
