@@ -58,8 +58,10 @@ TIMING_EVERY = 8
 # the bench reports null.
 COUNTER_SOURCES = ("pf_kernels.hip", "pf_models.hpp", "pf_internal.h")
 TRAFFIC = {
-    "ll_pl_2p20": dict(fetch_kib=13340.81, write_kib=27008.0, sources="e4e36bc5ae7211ba"),
-    "sv_pl_2p26": dict(fetch_kib=985895.34, write_kib=1990656.0, sources="e4e36bc5ae7211ba"),
+    "ll_pl_2p20": dict(fetch_kib=13333.81, write_kib=27008.0, sources="f4b5fc1f194e90c8"),
+    "sv_pl_2p26": dict(fetch_kib=986036.78, write_kib=1990656.0, sources="f4b5fc1f194e90c8"),
+    # one batched step: k_step_batch + k_scan_batch
+    "ll_pl_batch256": dict(fetch_kib=232077.09, write_kib=454431.2, sources="f4b5fc1f194e90c8"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -331,7 +333,7 @@ def run_batch(args, w, pf, torch):
         "plain": {"value": total * K / wall_plain, "ms_per_step": wall_plain * 1e3 / K},
         "batched_over_plain": wall_plain / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(args.workload),
                      "kernel": "k_step_batch + k_scan_batch", "kernel_avg_us": step_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_step},
         "batched_equals_plain_loglik": bool(np.array_equal(np.array(lls), np.array(lls_plain))),

@@ -65,8 +65,22 @@ extern "C" {
 enum pf_model { PF_LL_PF = 0, PF_LL_PL = 1, PF_SV_PF = 2, PF_SV_PL = 3 };
 
 /* Resampling uniforms (Section 3.1): multinomial i.i.d.; stratified, one per
- * stratum [j/N, (j+1)/N]; systematic, one offset shared by all strata. */
-enum pf_scheme { PF_MULTINOMIAL = 0, PF_STRATIFIED = 1, PF_SYSTEMATIC = 2 };
+ * stratum [j/N, (j+1)/N]; systematic, one offset shared by all strata;
+ * sorted multinomial, the multinomial scheme with its uniforms formed as
+ * order statistics (u_j = P_j / P_N, P_j the sum of the exponential spacings
+ * -log U_0 .. -log U_j, U_i from slot i's multinomial word, i = 0..N), so
+ * that slots receive ancestors in increasing order and the search merges
+ * like the stratified scheme; the offspring counts are multinomial exactly.
+ * Sorted multinomial needs the tile scan and is not batched.
+ * PF_SORTED_MULTINOMIAL IS CURRENTLY SWITCHED OFF: configurations that use
+ * it are refused with PF_EINVAL (its first GPU run faulted; the cause is
+ * not yet found). */
+enum pf_scheme {
+    PF_MULTINOMIAL = 0,
+    PF_STRATIFIED = 1,
+    PF_SYSTEMATIC = 2,
+    PF_SORTED_MULTINOMIAL = 3
+};
 
 /* Arithmetic of states and weights.  The CDF tile sums, normaliser and
  * log-likelihood are always accumulated in double precision. */

@@ -14,7 +14,12 @@ enum Stream : uint32_t {
 };
 
 enum Model : int32_t { kLLPF = 0, kLLPL = 1, kSVPF = 2, kSVPL = 3 };
-enum Scheme : int32_t { kMultinomial = 0, kStratified = 1, kSystematicScheme = 2 };
+enum Scheme : int32_t {
+    kMultinomial = 0,
+    kStratified = 1,
+    kSystematicScheme = 2,
+    kSortedMultinomial = 3
+};
 enum Strategy : int32_t { kAuto = 0, kBinary = 1, kCutpoint = 2, kMerge = 3 };
 
 // How the per-tile sums become the CDF's tile prefixes.
@@ -106,6 +111,8 @@ struct StepArgs {
     const TileAB* ab_in;        // tile-scan form of the previous CDF
     const int32_t* hint_in;     // source tile of CDF position b*TS/N, b = 0..tiles
     const Totals* tot_in;
+    const TileAB* abE;          // sorted multinomial: this step's uniforms as
+                                //   u = A_b + (in-tile spacing prefix) B_b
     void* c_out;
     void* samp_out;
     TileInfo* tiles_out;

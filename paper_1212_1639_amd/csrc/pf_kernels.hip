@@ -326,6 +326,81 @@ __device__ __forceinline__ double resample_uniform(int32_t scheme, int64_t j, in
     return EXACT ? pos / static_cast<double>(n) : pos * inv_n;
 }
 
+// ------------------------------------------------------------ sorted multinomial
+// Compiled out of the step kernels while the host refuses the scheme: its
+// first GPU run ended in a memory fault whose cause has not been found.
+constexpr bool kSortedKernels = false;
+
+// Exponential spacing -log U of a resampling word (double precision).
+__device__ __forceinline__ double spacing(uint32_t w0) { return -log(unit64(w0)); }
+
+// Inclusive prefix over a tile in slot order (slot i * BLOCK + tid holds
+// v[i]); v[i] is replaced by its prefix, *total receives the tile's sum.
+// Threads sum IPT consecutive slots (read through LDS with one pad entry per
+// IPT slots), then the threads' sums are scanned.  The same order gives the
+// same bits in every kernel that calls it.  Begins and ends with a barrier.
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void tile_incl_prefix(double (&v)[IPT], double* s_buf, double* s_red,
+                                                 double* total) {
+    constexpr int NW = BLOCK / kWave;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    auto pad = [](int slot) { return slot + slot / IPT; };
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) s_buf[pad(i * BLOCK + tid)] = v[i];
+    __syncthreads();
+    double run = 0.0, blk[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        run += s_buf[tid * (IPT + 1) + i];
+        blk[i] = run;
+    }
+    const double incl = wave_incl_sum(run);
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    double base = 0.0, tot = 0.0;
+    for (int q = 0; q < NW; ++q) {
+        if (q == wave) base = tot;
+        tot += s_red[q];
+    }
+    double ex = __shfl_up(incl, 1, kWave);
+    if (lane == 0) ex = 0.0;
+    base += ex;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) s_buf[tid * (IPT + 1) + i] = base + blk[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) v[i] = s_buf[pad(i * BLOCK + tid)];
+    *total = tot;
+    __syncthreads();
+}
+
+// Each tile's sum of the exponential spacings of time t (slots j0 .. j0+TS-1
+// below n; the last tile also adds the spacing of index n), as a (0, sum)
+// pair for the tile scan, which then yields the normalised offsets.
+template <int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_spacing_tiles(uint64_t seed, uint32_t t, int64_t n,
+                                                         double* aggE) {
+    constexpr int TS = BLOCK * IPT;
+    __shared__ double s_buf[BLOCK * (IPT + 1)];
+    __shared__ double s_red[BLOCK / kWave];
+    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * TS;
+    double v[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + threadIdx.x;
+        v[i] = j < n ? spacing(philox(seed, static_cast<uint32_t>(j), t, kStep, 0).w0) : 0.0;
+    }
+    double tot;
+    tile_incl_prefix<BLOCK, IPT>(v, s_buf, s_red, &tot);
+    if (threadIdx.x == 0) {
+        if (j0 + TS >= n)
+            tot += spacing(philox(seed, static_cast<uint32_t>(n), t, kStep, 0).w0);
+        aggE[2 * static_cast<int64_t>(blockIdx.x)] = 0.0;
+        aggE[2 * static_cast<int64_t>(blockIdx.x) + 1] = tot;
+    }
+}
+
 // ------------------------------------------------------------ shared memory
 template <int BLOCK, int IPT>
 struct StepSmem {
@@ -338,6 +413,7 @@ struct StepSmem {
     double last[8];          // each window tile's last value
     double red[NW * 16];     // reductions
     int64_t lo, hi;
+    double u_first, u_last;  // sorted multinomial: the tile's end uniforms
     uint32_t tile;
     int32_t pad;
     double ex_m, ex_s;
@@ -386,12 +462,34 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
             if (A.scheme == kSystematicScheme)
                 u_sys = unit64(philox(A.seed, 0, A.t, kSystematic, 0).w0);
             double u[IPT];
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                u[i] = resample_uniform<kExact>(A.scheme, j, n, inv_n, w[i].w0, u_sys);
-            }
             const int64_t jlast = min(j0 + TS, n) - 1;
+            const bool sorted_mult = kSortedKernels && A.scheme == kSortedMultinomial;
+            if (sorted_mult) {
+                // order statistics from exponential spacings: the tile's
+                // offset and scale come from the spacings' tile scan
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+                    u[i] = j < n ? spacing(w[i].w0) : 0.0;
+                }
+                double tot;
+                tile_incl_prefix<BLOCK, IPT>(u, sm.q, sm.red, &tot);
+                const TileAB e = gp(A.abE)[tile];
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) u[i] = fma(u[i], e.b, e.a);
+                const int64_t last_off = jlast - j0;
+                if (tid == 0) sm.u_first = u[0];
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if (static_cast<int64_t>(i) * BLOCK + tid == last_off) sm.u_last = u[i];
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+                    u[i] = resample_uniform<kExact>(A.scheme, j, n, inv_n, w[i].w0, u_sys);
+                }
+            }
             const int strategy = A.strategy;
             if (n <= WIN && strategy != kBinary) {
                 // the whole CDF fits one LDS window
@@ -419,9 +517,12 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 const bool indexed = A.scan == kScanTiles;
                 if (wave == 0 || wave == 1) {
                     const int64_t js = wave == 0 ? j0 : jlast;
-                    const double us = resample_uniform<kExact>(
-                        A.scheme, js, n, inv_n,
-                        philox(A.seed, static_cast<uint32_t>(js), A.t, kStep, 0).w0, u_sys);
+                    const double us =
+                        sorted_mult ? (wave == 0 ? sm.u_first : sm.u_last)
+                                    : resample_uniform<kExact>(
+                                          A.scheme, js, n, inv_n,
+                                          philox(A.seed, static_cast<uint32_t>(js), A.t, kStep, 0).w0,
+                                          u_sys);
                     int64_t a;
                     if (indexed) {
                         // the hint names the source tile of CDF position js/N;
@@ -840,9 +941,34 @@ constexpr int kScanBlock = 1024;
 // writes the table and the hints, three barriers.
 constexpr int kScanPer = 4;
 
+// Search positions of the output tiles: h ts / n (stratified, systematic),
+// or, for sorted multinomial, pos[h].a, the normalised spacing prefix before
+// output tile h.  first_h(b) = the first output tile h >= 1 whose position
+// is at least A_b (tile 0 starts at 0; T + 1 past the last tile).
+struct HintPos {
+    const TileAB* pos;  // sorted multinomial, else null
+    int32_t T;
+    double scale;       // n / ts
+    __device__ __forceinline__ int64_t first_h(int64_t b, double ab_a) const {
+        if (b == 0) return 0;
+        if (b >= T) return static_cast<int64_t>(T) + 1;
+        if (!pos) {
+            const double v = ceil(ab_a * scale);
+            return v > static_cast<double>(T) ? static_cast<int64_t>(T) : static_cast<int64_t>(v);
+        }
+        int lo = 1, hi = T;  // first h in [1, T) with pos[h].a >= ab_a, else T
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (pos[mid].a >= ab_a) hi = mid; else lo = mid + 1;
+        }
+        return lo;
+    }
+};
+
 __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_tiles, int64_t n,
                                                 int32_t ts, TileAB* ab, int32_t* hint,
-                                                Totals* tot, DevState* st) {
+                                                Totals* tot, DevState* st,
+                                                const TileAB* pos = nullptr) {
     constexpr int NW = kScanBlock / kWave;
     __shared__ double s_red[NW], s_first[kScanBlock];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -919,29 +1045,25 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     //    h = T.  The next thread's first A (after its own carry, which is
     //    this thread's carry raised by this thread's last value) closes the
     //    thread's last range.
-    if (b0 >= b1) return;
-    const double scale = static_cast<double>(n) / static_cast<double>(ts);
-    auto first_h = [&](int b, double ab_a) -> int64_t {
-        if (b == 0) return 0;
-        if (b >= T) return static_cast<int64_t>(T) + 1;
-        const double v = ceil(ab_a * scale);
-        return v > static_cast<double>(T) ? static_cast<int64_t>(T) : static_cast<int64_t>(v);
-    };
+    if (tid == 0) {
+        tot->M = M;
+        tot->S = S;
+        if (st) {
+            if (!ok) atomicOr(&st->flags, kDegenerate);
+            st->loglik += M + log(S / static_cast<double>(n));
+        }
+    }
+    if (b0 >= b1 || !hint) return;
+    const HintPos hp{pos, T, static_cast<double>(n) / static_cast<double>(ts)};
     const double next_a = b1 < T ? fmax(s_first[tid + 1], fmax(carry, amax)) : 0.0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         const int b = b0 + k;
         if (b < b1) {
             const double an = (b + 1 < b1) ? a[k + 1 < kScanPer ? k + 1 : k] : next_a;
-            const int64_t h0 = first_h(b, a[k]), h1 = first_h(b + 1, an);
+            const int64_t h0 = hp.first_h(b, a[k]), h1 = hp.first_h(b + 1, an);
             for (int64_t h = h0; h < h1; ++h) hint[h] = b;
         }
-    }
-    if (tid == 0) {
-        tot->M = M;
-        tot->S = S;
-        if (!ok) atomicOr(&st->flags, kDegenerate);
-        st->loglik += M + log(S / static_cast<double>(n));
     }
 }
 
@@ -1037,8 +1159,11 @@ __device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64
 __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(double* agg, int32_t num_tiles,
                                                            int64_t n, int32_t ts, TileAB* ab,
                                                            int32_t* hint, Totals* tot,
-                                                           DevState* st) {
-    scan_tiles(agg, num_tiles, n, ts, ab, hint, tot, st);
+                                                           DevState* st, const TileAB* pos) {
+    if (num_tiles <= kScanBlock * kScanPer)
+        scan_tiles_regs(agg, num_tiles, n, ts, ab, hint, tot, st, pos);
+    else
+        scan_tiles(agg, num_tiles, n, ts, ab, hint, tot, st);
 }
 
 // ------------------------------------------------------------ chunked tile scan
@@ -1171,8 +1296,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(const double* __restric
         const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
         tot->M = M;
         tot->S = S;
-        if (!ok) atomicOr(&st->flags, kDegenerate);
-        st->loglik += M + log(S / static_cast<double>(n));
+        if (st) {
+            if (!ok) atomicOr(&st->flags, kDegenerate);
+            st->loglik += M + log(S / static_cast<double>(n));
+        }
     }
 }
 
@@ -1182,7 +1309,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const double* __restr
                                                            const double* __restrict__ pref,
                                                            const Totals* __restrict__ tot,
                                                            TileAB* __restrict__ ab,
-                                                           int32_t* __restrict__ hint) {
+                                                           int32_t* __restrict__ hint,
+                                                           const TileAB* __restrict__ pos) {
     constexpr int NW = kScanBlock / kWave;
     __shared__ double s_red[NW];
     __shared__ double s_a[kScanBlock];
@@ -1208,16 +1336,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const double* __restr
     // chunk's first A equals min(P_{c+1}, P_{c+2}) / S = P_{c+1} / S.
     s_a[tid] = a;
     __syncthreads();
-    if (b >= T) return;
-    const double scale = static_cast<double>(n) / static_cast<double>(ts);
-    auto first_h = [&](int64_t bb, double abb) -> int64_t {
-        if (bb == 0) return 0;
-        if (bb >= T) return static_cast<int64_t>(T) + 1;
-        const double v = ceil(abb * scale);
-        return v > static_cast<double>(T) ? static_cast<int64_t>(T) : static_cast<int64_t>(v);
-    };
+    if (b >= T || !hint) return;
+    const HintPos hp{pos, T, static_cast<double>(n) / static_cast<double>(ts)};
     const double a_next = (tid + 1 < kScanBlock) ? s_a[tid + 1] : (ok ? hi / S : 0.0);
-    const int64_t h0 = first_h(b, a), h1 = first_h(b + 1, a_next);
+    const int64_t h0 = hp.first_h(b, a), h1 = hp.first_h(b + 1, a_next);
     for (int64_t h = h0; h < h1; ++h) hint[h] = static_cast<int32_t>(b);
 }
 
@@ -1603,11 +1725,11 @@ int32_t scan_chunks(int32_t num_tiles) {
 
 hipError_t launch_scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts, TileAB* ab,
                              int32_t* hint, Totals* tot, DevState* st, double* chunk,
-                             hipStream_t s) {
+                             const TileAB* pos, hipStream_t s) {
     const int32_t G = scan_chunks(num_tiles);
     if (G == 0) {
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, s, agg, num_tiles, n, ts,
-                           ab, hint, tot, st);
+                           ab, hint, tot, st, pos);
         return hipGetLastError();
     }
     double* pref = chunk + 2 * static_cast<int64_t>(G);
@@ -1617,8 +1739,25 @@ hipError_t launch_scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t 
                        static_cast<const double*>(chunk), G, n, pref, tot, st);
     hipLaunchKernelGGL(k_scan_apply, dim3(G), dim3(kScanBlock), 0, s,
                        static_cast<const double*>(agg), num_tiles, n, ts,
-                       static_cast<const double*>(pref), static_cast<const Totals*>(tot), ab, hint);
+                       static_cast<const double*>(pref), static_cast<const Totals*>(tot), ab, hint,
+                       pos);
     return hipGetLastError();
+}
+
+// The exponential spacings of time t: tile sums, then their tile scan
+// (normalised offsets and scale in abE; no hints, no log-likelihood).
+hipError_t launch_spacings(int ipt, uint64_t seed, uint32_t t, int64_t n, int32_t num_tiles,
+                           double* aggE, TileAB* abE, Totals* totE, double* chunk, hipStream_t s) {
+    switch (ipt) {
+    case 1: hipLaunchKernelGGL((k_spacing_tiles<256, 1>), dim3(num_tiles), dim3(256), 0, s, seed, t, n, aggE); break;
+    case 2: hipLaunchKernelGGL((k_spacing_tiles<256, 2>), dim3(num_tiles), dim3(256), 0, s, seed, t, n, aggE); break;
+    case 4: hipLaunchKernelGGL((k_spacing_tiles<256, 4>), dim3(num_tiles), dim3(256), 0, s, seed, t, n, aggE); break;
+    default: hipLaunchKernelGGL((k_spacing_tiles<256, 8>), dim3(num_tiles), dim3(256), 0, s, seed, t, n, aggE); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_scan_tiles(aggE, num_tiles, n, 256 * ipt, abE, nullptr, totE, nullptr, chunk,
+                             nullptr, s);
 }
 
 hipError_t launch_moments(int model, const double* partials, int32_t num_tiles, int64_t n,

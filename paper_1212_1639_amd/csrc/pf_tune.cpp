@@ -181,10 +181,11 @@ int pf_autotune(pf_config* cfg, const double* y, int64_t n_obs, void* hip_stream
         const int rc = consider(c);
         if (rc != PF_OK) return rc;
     }
-    // 3. scan: the decoupled look-back instead of the tile scan
+    // 3. scan: the decoupled look-back instead of the tile scan (sorted
+    //    multinomial resampling needs the tile scan)
     c.strategy = best.strategy;
-    c.flags |= PF_FLAG_LOOKBACK_SCAN;
-    {
+    if (c.scheme != PF_SORTED_MULTINOMIAL) {
+        c.flags |= PF_FLAG_LOOKBACK_SCAN;
         const int rc = consider(c);
         if (rc != PF_OK) return rc;
     }

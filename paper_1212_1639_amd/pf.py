@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libpf_mi355x.so")
 
 LL_PF, LL_PL, SV_PF, SV_PL = 0, 1, 2, 3
-MULTINOMIAL, STRATIFIED, SYSTEMATIC = 0, 1, 2
+MULTINOMIAL, STRATIFIED, SYSTEMATIC, SORTED_MULTINOMIAL = 0, 1, 2, 3
 FP32, FP64 = 0, 1
 SEARCH_AUTO, SEARCH_BINARY, SEARCH_CUTPOINT, SEARCH_MERGE = 0, 1, 2, 3
 OK, EINVAL, ENOMEM, EDEVICE, EDEGENERATE = 0, -1, -2, -3, -4

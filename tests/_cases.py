@@ -12,7 +12,7 @@ SV_PL_PARAMS = dict(SV_X0, prior_mean=[MU * (1 - PHI), PHI], prior_prec=[1.0, 0.
 PARAMS = {"ll_pf": LL_PARAMS, "ll_pl": LL_PL_PARAMS, "sv_pf": SV_PF_PARAMS,
           "sv_pl": SV_PL_PARAMS}
 MODEL_ID = {"ll_pf": 0, "ll_pl": 1, "sv_pf": 2, "sv_pl": 3}
-SCHEME_ID = {"multinomial": 0, "stratified": 1, "systematic": 2}
+SCHEME_ID = {"multinomial": 0, "stratified": 1, "systematic": 2, "sorted_multinomial": 3}
 
 
 def data(model, T, seed=0):

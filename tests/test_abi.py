@@ -56,7 +56,8 @@ def test_workspace_bytes_and_validation(pf):
                           x0_var=10, flags=pf.FLAG_KEEP_ANCESTORS)
     assert pf.workspace_bytes(keep) >= nb + 4 * (1 << 20)  # plus the ancestors
     bad = [
-        dict(n=0), dict(n=1 << 31), dict(scheme=7), dict(precision=3), dict(strategy=9),
+        dict(n=0), dict(n=1 << 31), dict(scheme=7), dict(scheme=4), dict(precision=3),
+        dict(strategy=9),
         dict(items_per_thread=3), dict(x0_var=-1.0), dict(a_v=0.5), dict(flags=4),
     ]
     for b in bad:
@@ -76,6 +77,11 @@ def test_workspace_bytes_and_validation(pf):
                          sigma_v2=1, sigma_w2=0.1, x0_var=10)
     with pytest.raises(pf.PFError, match="sorted"):
         pf.workspace_bytes(cfg)
+    # sorted multinomial is switched off: refused with a message that says so
+    sm = pf.make_config("ll_pf", 1 << 16, 1, scheme=pf.SORTED_MULTINOMIAL, sigma_v2=1,
+                        sigma_w2=0.1, x0_var=10)
+    with pytest.raises(pf.PFError, match="switched off"):
+        pf.workspace_bytes(sm)
     cfg = pf.make_config("sv_pl", 100, 1, prior_prec=[1.0, 2.0, 1.0], a_s=2, d_s=0.04, x0_var=1)
     with pytest.raises(pf.PFError, match="positive definite"):
         pf.workspace_bytes(cfg)

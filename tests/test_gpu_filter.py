@@ -30,6 +30,11 @@ def _strategy(pf, name):
             "merge": pf.SEARCH_MERGE}[name]
 
 
+SORTED_OFF = pytest.mark.skip(
+    reason="sorted multinomial is switched off: its first GPU run (double precision, "
+           "stochastic-volatility particle learning, N = 5000, 4 items per thread) ended in a "
+           "memory fault whose cause has not been found on the CPU")
+
 CASES = [
     # model, n, scheme, strategy, items_per_thread, T, scan
     ("ll_pf", 1024, "multinomial", "auto", 0, 100, "tiles"),   # the 1024-particle FP64 workload
@@ -51,6 +56,14 @@ CASES = [
     ("ll_pl", 2049, "systematic", "binary", 2, 20, "lookback"),
     ("sv_pl", 3000, "systematic", "merge", 1, 20, "lookback"),
     ("sv_pf", 9001, "stratified", "merge", 8, 12, "lookback"),
+    # sorted multinomial (order statistics from exponential spacings): switched
+    # off after the fourth case below faulted the GPU on its first run
+    pytest.param("ll_pf", 3000, "sorted_multinomial", "merge", 1, 20, "tiles", marks=SORTED_OFF),
+    pytest.param("ll_pf", 700, "sorted_multinomial", "auto", 1, 12, "tiles", marks=SORTED_OFF),
+    pytest.param("ll_pl", 2049, "sorted_multinomial", "auto", 2, 20, "tiles", marks=SORTED_OFF),
+    pytest.param("sv_pl", 5000, "sorted_multinomial", "merge", 4, 12, "tiles", marks=SORTED_OFF),
+    pytest.param("sv_pf", 20000, "sorted_multinomial", "binary", 8, 8, "tiles", marks=SORTED_OFF),
+    pytest.param("ll_pl", 100000, "sorted_multinomial", "merge", 4, 6, "tiles", marks=SORTED_OFF),
 ]
 
 
@@ -90,7 +103,8 @@ def _rel_err(a, b, sd):
 
 
 FP32_MODELS = [("ll_pl", "stratified"), ("ll_pf", "stratified"), ("sv_pl", "systematic"),
-               ("sv_pf", "systematic")]
+               ("sv_pf", "systematic"),
+               pytest.param("ll_pl", "sorted_multinomial", marks=SORTED_OFF)]
 
 
 @pytest.mark.parametrize("model,scheme", FP32_MODELS)
