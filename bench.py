@@ -151,7 +151,24 @@ def run_served(args, w, pf, torch):
                                       "particle_steps", "step_latency_ms", "queue_delay_ms",
                                       "max_bytes_in_use")},
     }
+    if not args.no_cpu_baseline:
+        # the oracle on the requests in arrival order, each over its first
+        # SERVE_CPU_OBS observations, one request per host core, about 15 s
+        import oracle
+        models = {"ll": (oracle.LL_PL, oracle.STRATIFIED), "sv": (oracle.SV_PL, oracle.SYSTEMATIC)}
+        jobs = ((oracle.make_config(models[r.model][0], r.n, r.id, scheme=models[r.model][1],
+                                    fp32_words=True, **groups[r.model]["params"]),
+                 r.y[:SERVE_CPU_OBS]) for r in reqs)
+        rate, workers, done = oracle_pool_rate(jobs)
+        out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": workers,
+                               "kind": "oracle",
+                               "sample": f"first {done} requests in arrival order, first "
+                                         f"{SERVE_CPU_OBS} observations each, one request per "
+                                         f"worker thread (FP64 C oracle)"}
     print(json.dumps(out), flush=True)
+
+
+SERVE_CPU_OBS = 20
 
 
 # The paper's GPU(sp) / GPU(dp) times in ms (Table 2; GTX 580) and the
@@ -339,23 +356,17 @@ def run_batch(args, w, pf, torch):
         "batched_equals_plain_loglik": bool(np.array_equal(np.array(lls), np.array(lls_plain))),
     }
     if not args.no_cpu_baseline:
-        # the oracle on the first filters of the same workload, one after the other
+        # the oracle on the filters of the same workload in order, one filter
+        # per host core, for about 15 s
         import oracle
-        budget, used, steps_done, t_cpu = 15.0, 0.0, 0, 0.0
-        done_particles = 0
-        for f, n in enumerate(sizes):
-            cfg = oracle.make_config(oracle.LL_PL, int(n), f, scheme=oracle.STRATIFIED,
-                                     fp32_words=True, **w["params"])
-            t0 = time.perf_counter()
-            oracle.run(cfg, y[:K, f])
-            t_cpu += time.perf_counter() - t0
-            done_particles += int(n)
-            if t_cpu > budget:
-                break
-        out["cpu_baseline"] = {"value": done_particles * K / t_cpu, "unit": "particle-steps/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"first {f + 1} of {nf} filters, all {K} steps each "
-                                         f"(sequential FP64 C oracle)"}
+        jobs = ((oracle.make_config(oracle.LL_PL, int(n), f, scheme=oracle.STRATIFIED,
+                                    fp32_words=True, **w["params"]), y[:K, f])
+                for f, n in enumerate(sizes))
+        rate, workers, done = oracle_pool_rate(jobs)
+        out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": workers,
+                               "kind": "oracle",
+                               "sample": f"first {done} of {nf} filters, all {K} steps each, one "
+                                         f"filter per worker thread (FP64 C oracle)"}
     print(json.dumps(out), flush=True)
 
 
@@ -501,9 +512,74 @@ def main():
         "loglik": loglik,
         "moments": [float(v) for v in mom],
     }
+    out["latency"] = step_latency(pf, cfg, y, stream, torch, min(K, LATENCY_STEPS))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, y)
     print(json.dumps(out), flush=True)
+
+
+LATENCY_STEPS = 200
+
+
+def step_latency(pf, cfg, y, stream, torch, steps):
+    """Per-step latency of one filter driven one observation at a time (host
+    clock from the call to the stream's completion), outside the timed
+    region: plain launches (`pf_step`) and a one-filter batch (the captured
+    graph replayed per step).  The first two steps of each (initialisation,
+    first weighting) are left out."""
+    res = {"steps": max(0, steps - 2)}
+    for form in ("plain", "graph"):
+        f = pf.Filter(cfg, stream=stream)
+        b = pf.Batch([f]) if form == "graph" else None
+        lat = []
+        for k in range(steps):
+            t0 = time.perf_counter()
+            if b is None:
+                f.step(y[k:k + 1])
+            else:
+                b.step(y[k:k + 1, None])
+            stream.synchronize()
+            lat.append(time.perf_counter() - t0)
+        if b is not None:
+            b.close()
+        f.close()
+        lat = np.asarray(lat[2:]) * 1e3
+        res[form] = ({"p50_ms": float(np.percentile(lat, 50)),
+                      "p99_ms": float(np.percentile(lat, 99))} if lat.size else None)
+    return res
+
+
+def oracle_pool_rate(jobs, budget_s=15.0):
+    """The oracle on independent filters spread over the host's cores, one
+    filter per worker thread (the C oracle releases the interpreter lock
+    and keeps no global state).  `jobs` yields (cfg, y) pairs; submission
+    stops once `budget_s` of wall time has passed.  Returns (particle-steps
+    per second, workers, filters completed)."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.lib()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    done_ps, done = 0, 0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        pending = set()
+        it = iter(jobs)
+        exhausted = False
+        while True:
+            while not exhausted and len(pending) < workers and time.perf_counter() - t0 < budget_s:
+                try:
+                    cfg, yy = next(it)
+                except StopIteration:
+                    exhausted = True
+                    break
+                pending.add(ex.submit(lambda c=cfg, v=yy: (oracle.run(c, v), c.n * v.size)[1]))
+            if not pending:
+                break
+            fin, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
+            for fu in fin:
+                done_ps += fu.result()
+                done += 1
+    return done_ps / (time.perf_counter() - t0), workers, done
 
 
 if __name__ == "__main__":

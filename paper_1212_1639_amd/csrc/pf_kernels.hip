@@ -72,37 +72,66 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return static_cast<int64_t>((hi << 32) | lo);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+// Cross-lane moves of a double through the VALU's data-parallel primitives
+// (DPP: two 32-bit moves, no LDS round trip).  Lanes whose source lies
+// outside the pattern, or whose row is masked off, receive `old`.
+constexpr int kDppRowShr = 0x110;     // + k: from lane - k of the same 16-lane row
+constexpr int kDppRowBcast15 = 0x142; // lane 15 of each row to the next row
+constexpr int kDppRowBcast31 = 0x143; // lane 31 to rows 2 and 3
+constexpr int kDppWaveShr1 = 0x138;   // from lane - 1 across the wave
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    const uint64_t o = static_cast<uint64_t>(__double_as_longlong(old));
+    const uint64_t x = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+        static_cast<int>(static_cast<uint32_t>(o)), static_cast<int>(static_cast<uint32_t>(x)),
+        CTRL, ROW_MASK, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+        static_cast<int>(static_cast<uint32_t>(o >> 32)),
+        static_cast<int>(static_cast<uint32_t>(x >> 32)), CTRL, ROW_MASK, 0xF, false));
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-    return v;
+// The value of lane 63, in every lane (a wave-uniform scalar).
+__device__ __forceinline__ double lane63(double v) {
+    const uint64_t x = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint32_t lo = static_cast<uint32_t>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(x)), kWave - 1));
+    const uint32_t hi = static_cast<uint32_t>(
+        __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(x >> 32)), kWave - 1));
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
-// Inclusive prefix sum over the wave (Kogge-Stone).
+// Inclusive prefix sum over the wave: Hillis-Steele within each 16-lane row,
+// then the row totals carried across rows.
 __device__ __forceinline__ double wave_incl_sum(double v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const double o = __shfl_up(v, off, kWave);
-        if (lane >= off) v += o;
-    }
+    v += dpp_f64<kDppRowShr + 1, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowShr + 2, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowShr + 4, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowShr + 8, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowBcast15, 0xA>(0.0, v);
+    v += dpp_f64<kDppRowBcast31, 0xC>(0.0, v);
     return v;
 }
 
 __device__ __forceinline__ double wave_incl_max(double v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const double o = __shfl_up(v, off, kWave);
-        if (lane >= off) v = fmax(v, o);
-    }
+    constexpr double lo = -INFINITY;
+    v = fmax(v, dpp_f64<kDppRowShr + 1, 0xF>(lo, v));
+    v = fmax(v, dpp_f64<kDppRowShr + 2, 0xF>(lo, v));
+    v = fmax(v, dpp_f64<kDppRowShr + 4, 0xF>(lo, v));
+    v = fmax(v, dpp_f64<kDppRowShr + 8, 0xF>(lo, v));
+    v = fmax(v, dpp_f64<kDppRowBcast15, 0xA>(lo, v));
+    v = fmax(v, dpp_f64<kDppRowBcast31, 0xC>(lo, v));
     return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return lane63(wave_incl_sum(v)); }
+__device__ __forceinline__ double wave_max(double v) { return lane63(wave_incl_max(v)); }
+
+// The previous lane's value (lane 0 receives `first`).
+__device__ __forceinline__ double wave_shr1(double v, double first) {
+    return dpp_f64<kDppWaveShr1, 0xF>(first, v);
 }
 
 // (max, sum of exp(l - max)) monoid of the max-shifted log-sum-exp.
@@ -363,8 +392,7 @@ __device__ __forceinline__ void tile_incl_prefix(double (&v)[IPT], double* s_buf
         if (q == wave) base = tot;
         tot += s_red[q];
     }
-    double ex = __shfl_up(incl, 1, kWave);
-    if (lane == 0) ex = 0.0;
+    double ex = wave_shr1(incl, 0.0);
     base += ex;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) s_buf[tid * (IPT + 1) + i] = base + blk[i];
@@ -744,8 +772,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     for (int q = 0; q < wave; ++q) base += sm.red[NW + q];
     double total = 0.0;
     for (int q = 0; q < NW; ++q) total += sm.red[NW + q];
-    double texcl = __shfl_up(tincl, 1, kWave);
-    if (lane == 0) texcl = 0.0;
+    double texcl = wave_shr1(tincl, 0.0);
     base += texcl;
     // the threads' bases and runs are rounded separately, so a thread's first
     // prefix can fall an ulp below its predecessor's last: raise each value to
@@ -757,8 +784,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     __syncthreads();
     double carry = -INFINITY;
     for (int q = 0; q < wave; ++q) carry = fmax(carry, sm.red[2 * NW + q]);
-    double wex = __shfl_up(wmax, 1, kWave);
-    if (lane == 0) wex = -INFINITY;
+    double wex = wave_shr1(wmax, -INFINITY);
     carry = fmax(carry, wex);
     // back to slot order through LDS, so that the stores are coalesced;
     // single precision rounds toward zero so that a tile's last prefix never
@@ -1011,8 +1037,7 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
         if (q == wave) wbase = S;
         S += s_red[q];
     }
-    double excl = __shfl_up(incl, 1, kWave);
-    if (lane == 0) excl = 0.0;
+    double excl = wave_shr1(incl, 0.0);
     excl += wbase;
     const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
     // 3. A_b, running max in the thread, then over the threads before it
@@ -1032,8 +1057,7 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     __syncthreads();
     double carry = -INFINITY;
     for (int q = 0; q < wave; ++q) carry = fmax(carry, s_red[q]);
-    double ex = __shfl_up(top, 1, kWave);
-    if (lane == 0) ex = -INFINITY;
+    double ex = wave_shr1(top, -INFINITY);
     carry = fmax(carry, ex);
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
@@ -1106,8 +1130,7 @@ __device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64
         if (q == wave) wbase = S;
         S += s_red[q];
     }
-    double excl = __shfl_up(incl, 1, kWave);
-    if (lane == 0) excl = 0.0;
+    double excl = wave_shr1(incl, 0.0);
     excl += wbase;
     const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
     // 4. normalised affine constants, made non-decreasing (running max over
@@ -1124,8 +1147,7 @@ __device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64
     __syncthreads();
     double carry = -INFINITY;
     for (int q = 0; q < wave; ++q) carry = fmax(carry, s_top[q]);
-    double ex = __shfl_up(top, 1, kWave);
-    if (lane == 0) ex = -INFINITY;
+    double ex = wave_shr1(top, -INFINITY);
     carry = fmax(carry, ex);
     if (carry > -INFINITY) {
         for (int b = b0; b < b1; ++b) {
@@ -1206,8 +1228,7 @@ __device__ __forceinline__ double block_excl_sum(double v, double* s_red, double
         tot += s_red[q];
     }
     __syncthreads();
-    double ex = __shfl_up(incl, 1, kWave);
-    if (lane == 0) ex = 0.0;
+    double ex = wave_shr1(incl, 0.0);
     *total = tot;
     return base + ex;
 }
@@ -1222,8 +1243,7 @@ __device__ __forceinline__ double block_excl_max(double v, double* s_red) {
     double carry = -INFINITY;
     for (int q = 0; q < wave; ++q) carry = fmax(carry, s_red[q]);
     __syncthreads();
-    double ex = __shfl_up(incl, 1, kWave);
-    if (lane == 0) ex = -INFINITY;
+    double ex = wave_shr1(incl, -INFINITY);
     return fmax(ex, carry);
 }
 
