@@ -467,6 +467,20 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     const int64_t j0 = static_cast<int64_t>(tile) * TS;
 
     // ---------------------------------------------------------- 1. ancestors
+    // The resampling's first reads (the previous CDF's totals and, for the
+    // merge search over the tile table, the hints of this tile and the
+    // next) are issued before the random words are formed, so their latency
+    // overlaps that work.
+    const bool merge_indexed =
+        resample && A.scan == kScanTiles && A.strategy == kMerge && n > WIN;
+    int32_t hint_pre = 0;
+    if (merge_indexed && wave < 2) hint_pre = gp(A.hint_in)[tile + wave];
+    double tot_M = 0.0, tot_S = 0.0;
+    if (resample) {
+        const Totals tt = *gp(A.tot_in);
+        tot_M = tt.M;
+        tot_S = tt.S;
+    }
     Words w[IPT];
     int32_t anc[IPT];
 #pragma unroll
@@ -477,9 +491,8 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
         else w[i] = {0u, 0u, 0u, 0u};
     }
     if (resample) {
-        const G<const Totals>* tot_in = gp(A.tot_in);
         PrevCdf<R> P{gp(static_cast<const R*>(A.c_in)), gp(A.tiles_in),
-                     A.scan == kScanTiles ? gp(A.ab_in) : nullptr, tot_in->M, tot_in->S, n, TS};
+                     A.scan == kScanTiles ? gp(A.ab_in) : nullptr, tot_M, tot_S, n, TS};
         const bool ok = (P.S > 0.0) && isfinite(P.S) && isfinite(P.M);
         if (!ok) {
             if (tid == 0) atomicOr(&A.st->flags, kDegenerate);
@@ -557,7 +570,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                         // its segment samples bracket u to one segment
                         constexpr int SEG = TS / kSegments;
                         const int64_t tmax = A.num_tiles - 1;
-                        const int64_t h = min(max(int64_t(gp(A.hint_in)[tile + wave]), int64_t(0)), tmax);
+                        const int64_t h = min(max(int64_t(hint_pre), int64_t(0)), tmax);
                         double ta, tb;
                         P.tile_ab(h, ta, tb);
                         G<const R>* samp = gp(static_cast<const R*>(A.samp_in));
@@ -962,10 +975,12 @@ __global__ __launch_bounds__(BLOCK, batch_min_blocks<IPT>()) void k_step_batch(
 // tiles' maxima are overwritten (agg[2b] becomes e^{m_b - M}).
 constexpr int kScanBlock = 1024;
 
-// Up to kScanBlock * kScanPer tiles, each thread keeps its (at most
-// kScanPer) tiles in registers: one pass reads the (max, sum) pairs, one
-// writes the table and the hints, three barriers.
-constexpr int kScanPer = 4;
+// The single-work-group tile scan: up to kTileScanBlock * kTileScanPer
+// tiles, each thread keeping its (at most kTileScanPer) tiles in registers:
+// one pass reads the (max, sum) pairs, one writes the table and the hints,
+// three barriers.
+constexpr int kTileScanBlock = 512;
+constexpr int kTileScanPer = 4096 / kTileScanBlock;
 
 // Search positions of the output tiles: h ts / n (stratified, systematic),
 // or, for sorted multinomial, pos[h].a, the normalised spacing prefix before
@@ -995,17 +1010,17 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
                                                 int32_t ts, TileAB* ab, int32_t* hint,
                                                 Totals* tot, DevState* st,
                                                 const TileAB* pos = nullptr) {
-    constexpr int NW = kScanBlock / kWave;
-    __shared__ double s_red[NW], s_first[kScanBlock];
+    constexpr int NW = kTileScanBlock / kWave;
+    __shared__ double s_red[NW], s_first[kTileScanBlock];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int T = num_tiles;
-    const int per = (T + kScanBlock - 1) / kScanBlock;
+    const int per = (T + kTileScanBlock - 1) / kTileScanBlock;
     const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
-    double m[kScanPer], w[kScanPer], e[kScanPer];
+    double m[kTileScanPer], w[kTileScanPer], e[kTileScanPer];
     // 1. M = max_b m_b
     double mx = -INFINITY;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
+    for (int k = 0; k < kTileScanPer; ++k) {
         m[k] = -INFINITY;
         w[k] = 0.0;
         if (b0 + k < b1) {
@@ -1024,7 +1039,7 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     // 2. e_b = e^{m_b - M}, w_b = s_b e_b; exclusive scan of the threads' sums
     double part = 0.0;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
+    for (int k = 0; k < kTileScanPer; ++k) {
         e[k] = (m[k] == -INFINITY || M == -INFINITY) ? 0.0 : exp(m[k] - M);
         w[k] *= e[k];
         part += w[k];
@@ -1041,10 +1056,10 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     excl += wbase;
     const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
     // 3. A_b, running max in the thread, then over the threads before it
-    double a[kScanPer];
+    double a[kTileScanPer];
     double run = excl, amax = -INFINITY;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
+    for (int k = 0; k < kTileScanPer; ++k) {
         amax = fmax(amax, ok ? run / S : 0.0);
         a[k] = amax;
         run += w[k];
@@ -1060,7 +1075,7 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     double ex = wave_shr1(top, -INFINITY);
     carry = fmax(carry, ex);
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
+    for (int k = 0; k < kTileScanPer; ++k) {
         a[k] = fmax(a[k], carry);
         if (b0 + k < b1) ab[b0 + k] = TileAB{a[k], ok ? e[k] / S : 0.0};
     }
@@ -1081,10 +1096,10 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     const HintPos hp{pos, T, static_cast<double>(n) / static_cast<double>(ts)};
     const double next_a = b1 < T ? fmax(s_first[tid + 1], fmax(carry, amax)) : 0.0;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
+    for (int k = 0; k < kTileScanPer; ++k) {
         const int b = b0 + k;
         if (b < b1) {
-            const double an = (b + 1 < b1) ? a[k + 1 < kScanPer ? k + 1 : k] : next_a;
+            const double an = (b + 1 < b1) ? a[k + 1 < kTileScanPer ? k + 1 : k] : next_a;
             const int64_t h0 = hp.first_h(b, a[k]), h1 = hp.first_h(b + 1, an);
             for (int64_t h = h0; h < h1; ++h) hint[h] = b;
         }
@@ -1093,15 +1108,15 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
 
 __device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts,
                                            TileAB* ab, int32_t* hint, Totals* tot, DevState* st) {
-    if (num_tiles <= kScanBlock * kScanPer) {
+    if (num_tiles <= kTileScanBlock * kTileScanPer) {
         scan_tiles_regs(agg, num_tiles, n, ts, ab, hint, tot, st);
         return;
     }
-    constexpr int NW = kScanBlock / kWave;
+    constexpr int NW = kTileScanBlock / kWave;
     __shared__ double s_red[NW], s_top[NW];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int T = num_tiles;
-    const int per = (T + kScanBlock - 1) / kScanBlock;
+    const int per = (T + kTileScanBlock - 1) / kTileScanBlock;
     const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
     // 1. M = max_b m_b
     double mx = -INFINITY;
@@ -1178,11 +1193,11 @@ __device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64
     }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(double* agg, int32_t num_tiles,
+__global__ __launch_bounds__(kTileScanBlock) void k_scan_tiles(double* agg, int32_t num_tiles,
                                                            int64_t n, int32_t ts, TileAB* ab,
                                                            int32_t* hint, Totals* tot,
                                                            DevState* st, const TileAB* pos) {
-    if (num_tiles <= kScanBlock * kScanPer)
+    if (num_tiles <= kTileScanBlock * kTileScanPer)
         scan_tiles_regs(agg, num_tiles, n, ts, ab, hint, tot, st, pos);
     else
         scan_tiles(agg, num_tiles, n, ts, ab, hint, tot, st);
@@ -1366,7 +1381,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const double* __restr
 // The batch's scans: work-group g scans filters g, g + grid, ... (those that
 // weighted this step); the last work-group to finish advances the batch's
 // step counter and resets its tile ticket.
-__global__ __launch_bounds__(kScanBlock) void k_scan_batch(const StepArgs* __restrict__ descs,
+__global__ __launch_bounds__(kTileScanBlock) void k_scan_batch(const StepArgs* __restrict__ descs,
                                                            BatchState* bs) {
     __shared__ uint32_t s_last;
     const uint64_t step = __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1706,7 +1721,7 @@ hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, co
     if (e != hipSuccess) return e;
     // n_filters here is the batch's capacity: the scan grid covers it
     const int sgrid = n_filters < 256 ? (n_filters > 0 ? n_filters : 1) : 256;
-    hipLaunchKernelGGL(k_scan_batch, dim3(sgrid), dim3(kScanBlock), 0, s, descs, bs);
+    hipLaunchKernelGGL(k_scan_batch, dim3(sgrid), dim3(kTileScanBlock), 0, s, descs, bs);
     return hipGetLastError();
 }
 
@@ -1737,7 +1752,7 @@ int batch_grid(int model, bool fp64, int ipt) {
 
 // Tile counts up to this use the single-work-group scan; above, the chunked
 // three-launch scan (chunk buffer: 2 doubles per chunk + G + 1 prefixes).
-constexpr int32_t kScanSingleMax = 4096;
+constexpr int32_t kScanSingleMax = kTileScanBlock * kTileScanPer;
 
 int32_t scan_chunks(int32_t num_tiles) {
     return num_tiles <= kScanSingleMax ? 0 : (num_tiles + kScanBlock - 1) / kScanBlock;
@@ -1748,7 +1763,7 @@ hipError_t launch_scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t 
                              const TileAB* pos, hipStream_t s) {
     const int32_t G = scan_chunks(num_tiles);
     if (G == 0) {
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanBlock), 0, s, agg, num_tiles, n, ts,
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kTileScanBlock), 0, s, agg, num_tiles, n, ts,
                            ab, hint, tot, st, pos);
         return hipGetLastError();
     }
