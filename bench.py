@@ -58,10 +58,17 @@ TIMING_EVERY = 8
 # the bench reports null.
 COUNTER_SOURCES = ("pf_kernels.hip", "pf_models.hpp", "pf_internal.h")
 TRAFFIC = {
-    "ll_pl_2p20": dict(fetch_kib=13333.81, write_kib=27008.0, sources="f4b5fc1f194e90c8"),
-    "sv_pl_2p26": dict(fetch_kib=986036.78, write_kib=1990656.0, sources="f4b5fc1f194e90c8"),
+    "ll_pl_2p20": dict(fetch_kib=12874.38, write_kib=25100.52, sources="5ad7b9e8850a8bba"),
+    "sv_pl_2p26": dict(fetch_kib=930842.85, write_kib=1928573.84, sources="5ad7b9e8850a8bba"),
     # one batched step: k_step_batch + k_scan_batch
-    "ll_pl_batch256": dict(fetch_kib=232077.09, write_kib=454431.2, sources="f4b5fc1f194e90c8"),
+    "ll_pl_batch256": dict(fetch_kib=231965.44, write_kib=450351.41, sources="5ad7b9e8850a8bba"),
+}
+# Share of the SIMD cycles the cycle kernel's vector instructions occupy
+# (SQ_INSTS_VALU x 4 cycles per wave instruction over the kernel's clock
+# cycles x 1024 SIMDs), from a counter run of the same kernel sources.
+VALU_ISSUE = {
+    "ll_pl_2p20": dict(share=0.51, valu_per_particle=645, sources="5ad7b9e8850a8bba"),
+    "sv_pl_2p26": dict(share=0.96, valu_per_particle=690, sources="5ad7b9e8850a8bba"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -73,6 +80,13 @@ def kernel_sources_hash():
         with open(os.path.join(ROOT, "paper_1212_1639_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def valu_issue(workload):
+    v = VALU_ISSUE.get(workload)
+    if v is None or v["sources"] != kernel_sources_hash():
+        return None
+    return {"share": v["share"], "valu_per_particle": v["valu_per_particle"]}
 
 
 def traffic_bytes(workload):
@@ -508,7 +522,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(args.workload),
                      "kernel": "k_step", "kernel_avg_us": kern_s * 1e6, "kernel_launches_timed": launches,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "valu_issue": valu_issue(args.workload)},
         "loglik": loglik,
         "moments": [float(v) for v in mom],
     }
