@@ -433,7 +433,7 @@ def main():
                          "copy kernel of known size, to scale the profiler's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs one filter per GPU and has no "
+        print("bench.py measures one GPU: the library runs each filter on one GPU and has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -112,7 +112,7 @@ int plan(const pf_config* c, Layout* L) {
     if (c->scheme < PF_MULTINOMIAL || c->scheme > PF_SORTED_MULTINOMIAL)
         return fail(PF_EINVAL, "unknown resampling scheme");
     if (c->scheme == PF_SORTED_MULTINOMIAL && !kSortedMultinomial)
-        return fail(PF_EINVAL, "sorted multinomial resampling is switched off in this build "
+        return fail(PF_EINVAL, "sorted multinomial resampling is switched off "
                                "(its first GPU runs ended in a memory fault whose cause has "
                                "not been found)");
     if (c->scheme == PF_SORTED_MULTINOMIAL && (c->flags & PF_FLAG_LOOKBACK_SCAN))
@@ -662,7 +662,7 @@ constexpr bool kAsyncParticleCopies = false;
 
 int pf_copy_particles_async(pf_filter* f, void* host_dst, size_t bytes, void* copy_stream) {
     if (!kAsyncParticleCopies)
-        return fail(PF_EDEVICE, "asynchronous particle copies are switched off in this build");
+        return fail(PF_EDEVICE, "asynchronous particle copies are switched off");
     if (!f || !host_dst) return fail(PF_EINVAL, "null argument");
     const size_t row = static_cast<size_t>(f->cfg.n_particles) * f->L.rsz;
     const size_t need = row * static_cast<size_t>(f->L.fields);

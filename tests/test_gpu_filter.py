@@ -3,7 +3,7 @@ through the C-ABI, against the CPU oracle on the same random streams.
 
 Double precision: ancestors bit-exact at every step and every particle's
 record within a relative 1e-9 (transcendental functions and summation
-order differ by ulps).  Single precision: the benchmark spec's tolerances
+order differ by ulps).  Single precision: the target tolerances
 |d loglik| <= 1e-3 T and filtered moments within 1e-4 relative (relative to
 max(|m|, posterior sd)) against the double-precision oracle driven by the
 same random words."""
