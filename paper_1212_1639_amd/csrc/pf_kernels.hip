@@ -127,6 +127,16 @@ __device__ __forceinline__ double wave_incl_max(double v) {
 }
 
 __device__ __forceinline__ double wave_sum(double v) { return lane63(wave_incl_sum(v)); }
+
+// Sum over each half wave (lanes 0-31 and 32-63), left in lanes 31 and 63.
+__device__ __forceinline__ double half_wave_sum(double v) {
+    v += dpp_f64<kDppRowShr + 1, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowShr + 2, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowShr + 4, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowShr + 8, 0xF>(0.0, v);
+    v += dpp_f64<kDppRowBcast15, 0xA>(0.0, v);
+    return v;
+}
 __device__ __forceinline__ double wave_max(double v) { return lane63(wave_incl_max(v)); }
 
 // The previous lane's value (lane 0 receives `first`).
@@ -707,42 +717,79 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
 
     // ---------------------------------------------------------- moment partials
     {
-        // combine the threads' partials in a fixed order (deterministic)
+        // The threads' partials (weighted ones relative to the thread's
+        // running max) are brought to the tile's max and summed in a fixed
+        // order: with room in the LDS window, every sum is folded by 32
+        // lanes over eight threads' entries each and then across the lanes;
+        // otherwise by wave reductions and a fold over the waves.
+        constexpr int NS = 2 + NG;  // e, e^2, e g[0 .. NG)
+        constexpr bool kLdsFold = BLOCK == 256 && NS <= BLOCK / 32 && NS * BLOCK <= WIN;
         const double tm = static_cast<double>(pm);
-        double m = weighted_mom ? wave_max(tm) : 0.0;
-        const double sc = weighted_mom ? (tm == -INFINITY ? 0.0 : exp(tm - m)) : 1.0;
-        const double v_e = wave_sum(static_cast<double>(pe) * sc);
-        const double v_e2 = wave_sum(static_cast<double>(pe2) * sc * sc);
-        double v_g[NG];
-#pragma unroll
-        for (int k = 0; k < NG; ++k) v_g[k] = wave_sum(static_cast<double>(pg[k]) * sc);
-        if (lane == 0) {
-            double* r = sm.red + wave * 16;
-            r[0] = m;
-            r[1] = v_e;
-            r[2] = v_e2;
-#pragma unroll
-            for (int k = 0; k < NG; ++k) r[3 + k] = v_g[k];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double Mx = -INFINITY;
-            if (weighted_mom)
-                for (int q = 0; q < NW; ++q) Mx = fmax(Mx, sm.red[q * 16]);
-            double out[3 + NG];
-            for (int k = 0; k < 3 + NG; ++k) out[k] = 0.0;
-            for (int q = 0; q < NW; ++q) {
-                const double* r = sm.red + q * 16;
-                const double f = weighted_mom ? (r[0] == -INFINITY ? 0.0 : exp(r[0] - Mx)) : 1.0;
-                out[1] += r[1] * f;
-                out[2] += r[2] * f * f;
-                for (int k = 0; k < NG; ++k) out[3 + k] += r[3 + k] * f;
+        G<double>* dst = gp(A.partials) + static_cast<int64_t>(tile) * kPartialStride;
+        if constexpr (kLdsFold) {
+            double Mx = 0.0, sc = 1.0;
+            if (weighted_mom) {
+                const double m = wave_max(tm);
+                if (lane == 0) sm.red[wave] = m;
             }
-            out[0] = weighted_mom ? Mx : 0.0;
-            G<double>* dst = gp(A.partials) + static_cast<int64_t>(tile) * kPartialStride;
-            for (int k = 0; k < 3 + NG; ++k) dst[k] = out[k];
+            __syncthreads();  // also: every wave is done with the search window
+            if (weighted_mom) {
+                Mx = -INFINITY;
+                for (int q = 0; q < NW; ++q) Mx = fmax(Mx, sm.red[q]);
+                sc = (tm == -INFINITY) ? 0.0 : exp(tm - Mx);
+            }
+            double* buf = sm.q;
+            buf[tid] = static_cast<double>(pe) * sc;
+            buf[BLOCK + tid] = static_cast<double>(pe2) * sc * sc;
+#pragma unroll
+            for (int k = 0; k < NG; ++k) buf[(2 + k) * BLOCK + tid] = static_cast<double>(pg[k]) * sc;
+            __syncthreads();
+            constexpr int PER = BLOCK / 32;
+            const int v = tid / 32, part = tid % 32;
+            double acc = 0.0;
+            if (v < NS) {
+#pragma unroll
+                for (int r = 0; r < PER; ++r) acc += buf[v * BLOCK + part * PER + r];
+            }
+            acc = half_wave_sum(acc);
+            if (v < NS && part == 31) dst[1 + v] = acc;
+            if (tid == 0) dst[0] = weighted_mom ? Mx : 0.0;
+            __syncthreads();
+        } else {
+            double m = weighted_mom ? wave_max(tm) : 0.0;
+            const double sc = weighted_mom ? (tm == -INFINITY ? 0.0 : exp(tm - m)) : 1.0;
+            const double v_e = wave_sum(static_cast<double>(pe) * sc);
+            const double v_e2 = wave_sum(static_cast<double>(pe2) * sc * sc);
+            double v_g[NG];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) v_g[k] = wave_sum(static_cast<double>(pg[k]) * sc);
+            if (lane == 0) {
+                double* r = sm.red + wave * 16;
+                r[0] = m;
+                r[1] = v_e;
+                r[2] = v_e2;
+#pragma unroll
+                for (int k = 0; k < NG; ++k) r[3 + k] = v_g[k];
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double Mx = -INFINITY;
+                if (weighted_mom)
+                    for (int q = 0; q < NW; ++q) Mx = fmax(Mx, sm.red[q * 16]);
+                double out[3 + NG];
+                for (int k = 0; k < 3 + NG; ++k) out[k] = 0.0;
+                for (int q = 0; q < NW; ++q) {
+                    const double* r = sm.red + q * 16;
+                    const double f = weighted_mom ? (r[0] == -INFINITY ? 0.0 : exp(r[0] - Mx)) : 1.0;
+                    out[1] += r[1] * f;
+                    out[2] += r[2] * f * f;
+                    for (int k = 0; k < NG; ++k) out[3 + k] += r[3 + k] * f;
+                }
+                out[0] = weighted_mom ? Mx : 0.0;
+                for (int k = 0; k < 3 + NG; ++k) dst[k] = out[k];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     if (!weight) return;
