@@ -679,12 +679,15 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
             const uint32_t a = static_cast<uint32_t>(anc[i]);
             R z[F], zn[F];
 #pragma unroll
-            for (int f = 0; f < F; ++f) z[f] = (rin + f * A.pitch)[a];
+            // records are read once and written once per cycle: streaming
+            // (non-temporal) accesses keep them from displacing the CDF
+            // window and tables in the caches
+            for (int f = 0; f < F; ++f) z[f] = __builtin_nontemporal_load(&(rin + f * A.pitch)[a]);
             R g[NG];
             if (propagate) {
                 MD::template propagate<R>(p, A.seed, j, A.t, A.y_prop, w[i], z, zn, g);
 #pragma unroll
-                for (int f = 0; f < F; ++f) (rout + f * A.pitch)[j] = zn[f];
+                for (int f = 0; f < F; ++f) __builtin_nontemporal_store(zn[f], &(rout + f * A.pitch)[j]);
             } else {
 #pragma unroll
                 for (int f = 0; f < F; ++f) zn[f] = z[f];
@@ -869,7 +872,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-        if (j < n) cout[j] = static_cast<R>(sm.q[pad(i * BLOCK + tid)]);
+        if (j < n) __builtin_nontemporal_store(static_cast<R>(sm.q[pad(i * BLOCK + tid)]), &cout[j]);
     }
     const Agg mine{mb, mb == -INFINITY ? 0.0 : total};
 
