@@ -845,14 +845,26 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
             for (int64_t i = 0; i < n; ++i)
                 b->h_stage[slot * cap + i] = b->fs[i]->prepare_obs(y[(done + s) * n + i]);
         }
-        // the slots [first, first+chunk) mod ring, in at most two pieces
+        // the slots [first, first+chunk) mod ring: only their first n
+        // descriptors are live, so a batch running below its capacity copies
+        // n per slot (one copy per slot), a full one whole runs of slots
+        // (at most two pieces)
         const uint64_t s0 = first % static_cast<uint64_t>(b->ring);
         const uint64_t c0 = std::min<uint64_t>(chunk, b->ring - s0);
-        e = hipMemcpyAsync(b->d_descs + s0 * cap, b->h_stage + s0 * cap,
-                           sizeof(pf::StepArgs) * c0 * cap, hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess && c0 < static_cast<uint64_t>(chunk))
-            e = hipMemcpyAsync(b->d_descs, b->h_stage, sizeof(pf::StepArgs) * (chunk - c0) * cap,
-                               hipMemcpyHostToDevice, b->stream);
+        if (n == cap) {
+            e = hipMemcpyAsync(b->d_descs + s0 * cap, b->h_stage + s0 * cap,
+                               sizeof(pf::StepArgs) * c0 * cap, hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess && c0 < static_cast<uint64_t>(chunk))
+                e = hipMemcpyAsync(b->d_descs, b->h_stage,
+                                   sizeof(pf::StepArgs) * (chunk - c0) * cap,
+                                   hipMemcpyHostToDevice, b->stream);
+        } else {
+            for (int64_t s = 0; s < chunk && e == hipSuccess; ++s) {
+                const uint64_t slot = (first + s) % static_cast<uint64_t>(b->ring);
+                e = hipMemcpyAsync(b->d_descs + slot * cap, b->h_stage + slot * cap,
+                                   sizeof(pf::StepArgs) * n, hipMemcpyHostToDevice, b->stream);
+            }
+        }
         for (int64_t s = 0; s < chunk && e == hipSuccess; ++s)
             e = hipEventRecord(b->slot_copied[(first + s) % static_cast<uint64_t>(b->ring)],
                                b->stream);
