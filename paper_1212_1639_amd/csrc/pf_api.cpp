@@ -310,6 +310,8 @@ struct pf_filter {
                   (weight ? pf::kWeight : 0);
         const bool weighted_mom = weight && cfg.model != PF_LL_PL;
         if (weighted_mom) a.flags |= pf::kWeightedMoments;
+        // small filters scan their tiles in the cycle kernel's last work-group
+        if (weight && fused_scan()) a.flags |= pf::kFusedScan;
         a.t = t + 1;
         a.y_prop = y_prop;
         a.y_weight = y_weight;
@@ -354,6 +356,10 @@ struct pf_filter {
         return prepare(have_cdf, true, true, y, y);
     }
 
+    bool fused_scan() const {
+        return !L.lookback && !L.spacings && L.num_tiles <= pf::kFusedScanMax;
+    }
+
     int run(const pf::StepArgs& a) {
         if (a.flags & pf::kPropagate) {
             const int b = a.rec_out == static_cast<void*>(ws + L.rec[0]) ? 0 : 1;
@@ -372,7 +378,7 @@ struct pf_filter {
                 return hip_fail(hipGetLastError(), "timing event");
             ++timed;
         }
-        if ((a.flags & pf::kWeight) && !L.lookback) {
+        if ((a.flags & pf::kWeight) && !L.lookback && !(a.flags & pf::kFusedScan)) {
             const pf::TileAB* pos = nullptr;
             if (L.spacings) {
                 // the uniforms of the next resampling (the cycle that uses this
@@ -501,6 +507,7 @@ int pf_loglik(pf_filter* f, double* out) {
     if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return hip_fail(e, "pf_loglik copy");
     *out = st.loglik;
+    if (st.flags & pf::kScanStall) return fail(PF_EDEVICE, "a fused tile scan stopped waiting for a tile's sums");
     if (st.flags & pf::kDegenerate) return fail(PF_EDEGENERATE, "a step's weights were all zero or not finite");
     return PF_OK;
 }
@@ -524,6 +531,7 @@ int pf_moments(pf_filter* f, double* out, int32_t n_out) {
     if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return hip_fail(e, "pf_moments copy");
     for (int k = 0; k < n_out; ++k) out[k] = k < need ? st.moments[k] : 0.0;
+    if (st.flags & pf::kScanStall) return fail(PF_EDEVICE, "a fused tile scan stopped waiting for a tile's sums");
     if (st.flags & pf::kDegenerate) return fail(PF_EDEGENERATE, "a step's weights were all zero or not finite");
     return PF_OK;
 }

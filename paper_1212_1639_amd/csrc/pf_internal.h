@@ -33,8 +33,15 @@ enum StepFlags : int32_t {
     kResample = 1,   // draw ancestors from the previous step's CDF
     kPropagate = 2,  // move the particles (else they are only re-weighted)
     kWeight = 4,     // compute log-weights, the CDF and the normaliser
-    kWeightedMoments = 8  // moment partials weighted by this step's weights
+    kWeightedMoments = 8,  // moment partials weighted by this step's weights
+    kFusedScan = 16        // the cycle's last work-group runs the tile scan
 };
+
+// Filters of at most this many tiles scan their tiles inside the cycle
+// kernel (the work-group that finishes last), which saves the scan launch;
+// for more tiles the work-groups' completion count, one atomic per
+// work-group on a single word, costs more than the launch.
+constexpr int32_t kFusedScanMax = 16;
 
 // Per-tile output of the CDF scan.  m_* are log-scale shifts, s_* sums of
 // exp(l - m): the tile's exclusive prefix over all earlier tiles (m_ex, s_ex)
@@ -62,10 +69,14 @@ struct DevState {
     uint32_t ticket;     // dynamic tile ticket of the running step (look-back)
     uint32_t flags;      // bit 0: a step's normaliser was zero or not finite
     double moments[8];   // output of the moment reduction
-    double pad[6];
+    uint32_t done;       // work-groups of the running cycle that have finished (fused scan)
+    uint32_t pad32;
+    double pad[5];
 };
 
-enum StateFlags : uint32_t { kDegenerate = 1 };
+// bit 0: a step's normaliser was zero or not finite; bit 1: a fused tile
+// scan gave up waiting for a tile's (max, sum)
+enum StateFlags : uint32_t { kDegenerate = 1, kScanStall = 2 };
 
 // Parameters of all four models (only the model's own ones are read).
 struct ModelParams {

@@ -164,6 +164,10 @@ __device__ __forceinline__ Agg wave_agg(Agg v) {
     return v;
 }
 
+// A fused tile scan waits at most this many polls (each followed by a short
+// sleep) for one tile's words before it reports a stall.
+constexpr uint32_t kFusedScanSpins = 1u << 22;
+
 // ------------------------------------------------------------ look-back words
 // Each 64-bit word = (epoch << 32) | 32 payload bits; relaxed agent-scope
 // atomics keep every word single-copy atomic and coherent across the XCDs'
@@ -439,6 +443,12 @@ __global__ __launch_bounds__(BLOCK) void k_spacing_tiles(uint64_t seed, uint32_t
     }
 }
 
+template <int NT, int PER, typename Load>
+__device__ __forceinline__ void tile_scan_core(Load load, int32_t num_tiles, int64_t n,
+                                               int32_t ts, TileAB* ab, int32_t* hint,
+                                               Totals* tot, DevState* st, const TileAB* pos,
+                                               double* s_red, double* s_first);
+
 // ------------------------------------------------------------ shared memory
 template <int BLOCK, int IPT>
 struct StepSmem {
@@ -453,7 +463,7 @@ struct StepSmem {
     int64_t lo, hi;
     double u_first, u_last;  // sorted multinomial: the tile's end uniforms
     uint32_t tile;
-    int32_t pad;
+    int32_t scan_here;       // fused tile scan: this work-group finished last
     double ex_m, ex_s;
 };
 
@@ -877,12 +887,76 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     const Agg mine{mb, mb == -INFINITY ? 0.0 : total};
 
     if (!lookback) {
-        // tile scan: publish the tile's (max, sum); k_scan_tiles does the rest
-        if (tid == 0) {
-            G<double>* agg = gp(A.agg_out);
-            agg[2 * static_cast<int64_t>(tile)] = mine.m;
-            agg[2 * static_cast<int64_t>(tile) + 1] = mine.s;
+        if (!(A.flags & kFusedScan)) {
+            // tile scan: publish the tile's (max, sum); k_scan_tiles does the rest
+            if (tid == 0) {
+                G<double>* agg = gp(A.agg_out);
+                agg[2 * static_cast<int64_t>(tile)] = mine.m;
+                agg[2 * static_cast<int64_t>(tile) + 1] = mine.s;
+            }
+            return;
         }
+        // fused tile scan: publish the tile's (max, sum) as epoch-tagged words,
+        // then count this work-group done; the one that finishes last scans.
+        // Every tile publishes before it counts itself, so each word the last
+        // work-group waits on is at most still in flight.
+        if (tid == 0) {
+            put_agg(A.status + static_cast<int64_t>(tile) * kStatusWords, A.epoch, mine);
+            const uint32_t dn = __hip_atomic_fetch_add(&A.st->done, 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            sm.scan_here = (dn + 1u == static_cast<uint32_t>(A.num_tiles)) ? 1 : 0;
+        }
+        __syncthreads();
+        const bool scan_here = sm.scan_here != 0;
+        // every wave has read the flag before any leaves (the batched kernel
+        // reuses the work-group's shared fields for its next tile)
+        __syncthreads();
+        if (!scan_here) return;
+        if (tid == 0) __hip_atomic_store(&A.st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t epoch = A.epoch;
+        const uint64_t* status = A.status;
+        DevState* st = A.st;
+        // all of the thread's words are requested at once; a tile whose words
+        // do not all carry this epoch yet is polled again (bounded)
+        auto load = [&](int b0, int b1, double (&m)[4], double (&w)[4]) {
+            uint64_t wd[4][4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t* p = status + static_cast<int64_t>(min(b0 + k, b1 - 1)) * kStatusWords;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wd[k][q] = b0 + k < b1 ? get_word(p + q) : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                m[k] = -INFINITY;
+                w[k] = 0.0;
+                if (b0 + k >= b1) continue;
+                const uint64_t tag = static_cast<uint64_t>(epoch);
+                Agg v;
+                if ((wd[k][0] >> 32) == tag && (wd[k][1] >> 32) == tag &&
+                    (wd[k][2] >> 32) == tag && (wd[k][3] >> 32) == tag) {
+                    v.m = __longlong_as_double(
+                        static_cast<long long>((wd[k][0] & 0xffffffffull) | (wd[k][1] << 32)));
+                    v.s = __longlong_as_double(
+                        static_cast<long long>((wd[k][2] & 0xffffffffull) | (wd[k][3] << 32)));
+                } else {
+                    const uint64_t* p = status + static_cast<int64_t>(b0 + k) * kStatusWords;
+                    for (uint32_t spin = 0; !get_agg(p, epoch, v); ++spin) {
+                        if (spin >= kFusedScanSpins) {
+                            atomicOr(&st->flags, kScanStall);
+                            v = agg_identity();
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                m[k] = v.m;
+                w[k] = v.s;
+            }
+        };
+        static_assert(BLOCK * 4 >= kFusedScanMax, "fused scan: 4 tiles per thread");
+        tile_scan_core<BLOCK, 4>(load, A.num_tiles, n, TS, A.ab_out, A.hint_out, A.tot_out, A.st,
+                                 nullptr, sm.red, sm.q);
         return;
     }
 
@@ -1056,30 +1130,25 @@ struct HintPos {
     }
 };
 
-__device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_tiles, int64_t n,
-                                                int32_t ts, TileAB* ab, int32_t* hint,
-                                                Totals* tot, DevState* st,
-                                                const TileAB* pos = nullptr) {
-    constexpr int NW = kTileScanBlock / kWave;
-    __shared__ double s_red[NW], s_first[kTileScanBlock];
+// The scan over NT threads, each holding at most PER tiles; load(b0, b1,
+// m, w) fills m[k], w[k] with tile b0 + k's (max, sum) for b0 + k < b1 and
+// with (-inf, 0) beyond.  s_red holds NT / 64 doubles, s_first NT.
+template <int NT, int PER, typename Load>
+__device__ __forceinline__ void tile_scan_core(Load load, int32_t num_tiles, int64_t n,
+                                               int32_t ts, TileAB* ab, int32_t* hint,
+                                               Totals* tot, DevState* st, const TileAB* pos,
+                                               double* s_red, double* s_first) {
+    constexpr int NW = NT / kWave;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int T = num_tiles;
-    const int per = (T + kTileScanBlock - 1) / kTileScanBlock;
+    const int per = (T + NT - 1) / NT;
     const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
-    double m[kTileScanPer], w[kTileScanPer], e[kTileScanPer];
+    double m[PER], w[PER], e[PER];
     // 1. M = max_b m_b
     double mx = -INFINITY;
+    load(b0, b1, m, w);
 #pragma unroll
-    for (int k = 0; k < kTileScanPer; ++k) {
-        m[k] = -INFINITY;
-        w[k] = 0.0;
-        if (b0 + k < b1) {
-            const double2 v = reinterpret_cast<const double2*>(agg)[b0 + k];
-            m[k] = v.x;
-            w[k] = v.y;
-        }
-        mx = fmax(mx, m[k]);
-    }
+    for (int k = 0; k < PER; ++k) mx = fmax(mx, m[k]);
     mx = wave_max(mx);
     if (lane == 0) s_red[wave] = mx;
     __syncthreads();
@@ -1089,7 +1158,7 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     // 2. e_b = e^{m_b - M}, w_b = s_b e_b; exclusive scan of the threads' sums
     double part = 0.0;
 #pragma unroll
-    for (int k = 0; k < kTileScanPer; ++k) {
+    for (int k = 0; k < PER; ++k) {
         e[k] = (m[k] == -INFINITY || M == -INFINITY) ? 0.0 : exp(m[k] - M);
         w[k] *= e[k];
         part += w[k];
@@ -1106,10 +1175,10 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     excl += wbase;
     const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
     // 3. A_b, running max in the thread, then over the threads before it
-    double a[kTileScanPer];
+    double a[PER];
     double run = excl, amax = -INFINITY;
 #pragma unroll
-    for (int k = 0; k < kTileScanPer; ++k) {
+    for (int k = 0; k < PER; ++k) {
         amax = fmax(amax, ok ? run / S : 0.0);
         a[k] = amax;
         run += w[k];
@@ -1125,7 +1194,7 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     double ex = wave_shr1(top, -INFINITY);
     carry = fmax(carry, ex);
 #pragma unroll
-    for (int k = 0; k < kTileScanPer; ++k) {
+    for (int k = 0; k < PER; ++k) {
         a[k] = fmax(a[k], carry);
         if (b0 + k < b1) ab[b0 + k] = TileAB{a[k], ok ? e[k] / S : 0.0};
     }
@@ -1146,14 +1215,35 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
     const HintPos hp{pos, T, static_cast<double>(n) / static_cast<double>(ts)};
     const double next_a = b1 < T ? fmax(s_first[tid + 1], fmax(carry, amax)) : 0.0;
 #pragma unroll
-    for (int k = 0; k < kTileScanPer; ++k) {
+    for (int k = 0; k < PER; ++k) {
         const int b = b0 + k;
         if (b < b1) {
-            const double an = (b + 1 < b1) ? a[k + 1 < kTileScanPer ? k + 1 : k] : next_a;
+            const double an = (b + 1 < b1) ? a[k + 1 < PER ? k + 1 : k] : next_a;
             const int64_t h0 = hp.first_h(b, a[k]), h1 = hp.first_h(b + 1, an);
             for (int64_t h = h0; h < h1; ++h) hint[h] = b;
         }
     }
+}
+
+__device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_tiles, int64_t n,
+                                                int32_t ts, TileAB* ab, int32_t* hint,
+                                                Totals* tot, DevState* st,
+                                                const TileAB* pos = nullptr) {
+    __shared__ double s_red[kTileScanBlock / kWave], s_first[kTileScanBlock];
+    auto load = [&](int b0, int b1, double (&m)[kTileScanPer], double (&w)[kTileScanPer]) {
+#pragma unroll
+        for (int k = 0; k < kTileScanPer; ++k) {
+            m[k] = -INFINITY;
+            w[k] = 0.0;
+            if (b0 + k < b1) {
+                const double2 v = reinterpret_cast<const double2*>(agg)[b0 + k];
+                m[k] = v.x;
+                w[k] = v.y;
+            }
+        }
+    };
+    tile_scan_core<kTileScanBlock, kTileScanPer>(load, num_tiles, n, ts, ab, hint, tot, st, pos,
+                                                 s_red, s_first);
 }
 
 __device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts,
@@ -1439,7 +1529,7 @@ __global__ __launch_bounds__(kTileScanBlock) void k_scan_batch(const StepArgs* _
     const StepArgs* d = descs + (step % static_cast<uint64_t>(bs->ring)) * bs->capacity;
     for (int32_t f = blockIdx.x; f < n_filters; f += gridDim.x) {
         const StepArgs& A = d[f];
-        if (A.flags & kWeight)
+        if ((A.flags & kWeight) && !(A.flags & kFusedScan))
             scan_tiles(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out, A.tot_out, A.st);
         __syncthreads();
     }
@@ -1487,6 +1577,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(StepArgs A) {
         A.st->loglik = 0.0;
         A.st->ticket = 0;
         A.st->flags = 0;
+        A.st->done = 0;
     }
     double vc = wave_sum(cnt);
     double vg[NG];
