@@ -168,7 +168,9 @@ int pf_step(pf_filter* f, const double* y, int64_t n_obs);
 /* Synchronise the filter's stream and return in *out the log-likelihood
  * estimate sum_t log( (1/N) sum_i p(y_t | particle i) ) over the
  * observations assimilated so far (0 before any).  Errors: PF_EDEGENERATE,
- * PF_EDEVICE. */
+ * PF_EDEVICE (also when a filter of at most 16 tiles, whose tile scan runs
+ * in the cycle kernel's last work-group, found a tile's sums missing after
+ * its bounded wait; sticky like PF_EDEGENERATE). */
 int pf_loglik(pf_filter* f, double* out);
 
 /* Synchronise and return posterior statistics of the latest time step in
@@ -183,7 +185,8 @@ int pf_loglik(pf_filter* f, double* out);
  *     [E x_t, Var x_t, E alpha, E beta, E sigma^2 of the draws,
  *      effective sample size, Rao-Blackwell mean of sigma^2].
  * For PF_LL_PL this may launch the propagation of the latest observation
- * (the cycle weights y_{t+1} before it propagates with y_t). */
+ * (the cycle weights y_{t+1} before it propagates with y_t).  Errors:
+ * PF_EINVAL, PF_EDEGENERATE, PF_EDEVICE (as pf_loglik). */
 int pf_moments(pf_filter* f, double* out, int32_t n_out);
 
 /* Release a handle and, if the library allocated it, its workspace.
