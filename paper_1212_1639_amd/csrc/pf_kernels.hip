@@ -128,6 +128,26 @@ __device__ __forceinline__ double wave_incl_max(double v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return lane63(wave_incl_sum(v)); }
 
+// Wave maximum in the weights' precision (single precision: one 32-bit
+// move per step), returned in double precision in every lane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                      ROW_MASK, 0xF, false));
+}
+__device__ __forceinline__ double wave_max_r(float v) {
+    constexpr float lo = -INFINITY;
+    v = fmaxf(v, dpp_f32<kDppRowShr + 1, 0xF>(lo, v));
+    v = fmaxf(v, dpp_f32<kDppRowShr + 2, 0xF>(lo, v));
+    v = fmaxf(v, dpp_f32<kDppRowShr + 4, 0xF>(lo, v));
+    v = fmaxf(v, dpp_f32<kDppRowShr + 8, 0xF>(lo, v));
+    v = fmaxf(v, dpp_f32<kDppRowBcast15, 0xA>(lo, v));
+    v = fmaxf(v, dpp_f32<kDppRowBcast31, 0xC>(lo, v));
+    return static_cast<double>(
+        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1)));
+}
+__device__ __forceinline__ double wave_max_r(double v) { return lane63(wave_incl_max(v)); }
+
 // Sum over each half wave (lanes 0-31 and 32-63), left in lanes 31 and 63.
 __device__ __forceinline__ double half_wave_sum(double v) {
     v += dpp_f64<kDppRowShr + 1, 0xF>(0.0, v);
@@ -740,13 +760,13 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
         const double tm = static_cast<double>(pm);
         G<double>* dst = gp(A.partials) + static_cast<int64_t>(tile) * kPartialStride;
         if constexpr (kLdsFold) {
+            // (every search path ends with a barrier, so the window in LDS
+            // is free again here)
             double Mx = 0.0, sc = 1.0;
             if (weighted_mom) {
                 const double m = wave_max(tm);
                 if (lane == 0) sm.red[wave] = m;
-            }
-            __syncthreads();  // also: every wave is done with the search window
-            if (weighted_mom) {
+                __syncthreads();
                 Mx = -INFINITY;
                 for (int q = 0; q < NW; ++q) Mx = fmax(Mx, sm.red[q]);
                 sc = (tm == -INFINITY) ? 0.0 : exp(tm - Mx);
@@ -808,10 +828,10 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     if (!weight) return;
 
     // ---------------------------------------------------------- 3. tile CDF
-    double mloc = -INFINITY;
+    R rloc = R(-INFINITY);
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) mloc = fmax(mloc, static_cast<double>(lw[i]));
-    mloc = wave_max(mloc);
+    for (int i = 0; i < IPT; ++i) rloc = fmax(rloc, lw[i]);
+    const double mloc = wave_max_r(rloc);
     if (lane == 0) sm.red[wave] = mloc;
     __syncthreads();
     double mb = -INFINITY;
