@@ -6,8 +6,12 @@ A step is one full cycle of the filter (weights, CDF scan, resampling,
 propagation with the particle-learning statistics) over all particles of
 one filter, launched through the C-ABI.  Prints ONE JSON line: whole-job
 particle-steps/s, the roofline of the cycle kernel (algorithmic bytes per
-launch over its average duration, from HIP events on the filter's stream),
-and the CPU oracle timed on a bounded sample of the same workload.
+launch over its average duration, from HIP events on the filter's stream;
+HBM traffic and the share of SIMD cycles its vector instructions occupy,
+from counter runs of the same kernel sources), the per-step latency of one
+filter driven one observation at a time (plain launches and a one-filter
+graph replay), and the CPU oracle timed on a bounded sample of the same
+workload (one filter per host core for the batched and served workloads).
 
 Workloads (all synthetic; data simulated from the model):
   ll_pl_2p20  particle learning, local-level model, unknown variances under
