@@ -83,8 +83,18 @@ int model_moments(int32_t model) {
     return 0;
 }
 
+// Double-precision stochastic-volatility particle learning with 4 items per
+// thread is switched off: that kernel gave wrong weights from its first
+// resampling on (and the one run that faulted the GPU used it), while the
+// same model at 1, 2 and 8 items per thread, and every other model at 4,
+// match the oracle; the cause is not yet found.
+bool switched_off_ipt(const pf_config& c, int ipt) {
+    return c.model == PF_SV_PL && c.precision == PF_FP64 && ipt == 4;
+}
+
 int choose_ipt(const pf_config& c) {
     if (c.items_per_thread) return c.items_per_thread;
+    if (switched_off_ipt(c, 4)) return 1;
     // measured on MI355X: 4 items per thread (with 5 resident work-groups
     // per CU) beats 2 and 8 from 2^20 to 2^26 particles
     return 4;
@@ -129,6 +139,9 @@ int plan(const pf_config* c, Layout* L) {
     const int ipt = choose_ipt(*c);
     if (ipt != 1 && ipt != 2 && ipt != 4 && ipt != 8)
         return fail(PF_EINVAL, "items_per_thread must be 0, 1, 2, 4 or 8");
+    if (switched_off_ipt(*c, ipt))
+        return fail(PF_EINVAL, "double-precision PF_SV_PL with 4 items per thread is switched off "
+                               "(wrong weights whose cause has not been found); use 1, 2 or 8");
     if (!finite_all({c->x0_mean, c->x0_var}) || !(c->x0_var > 0))
         return fail(PF_EINVAL, "x0_var must be finite and > 0");
     switch (c->model) {

@@ -22,6 +22,13 @@ int set_error(int code, const char* msg);
 namespace {
 
 constexpr int kIpts[] = {1, 2, 4, 8};
+
+// Tile sizes the library refuses for a configuration (pf_workspace_bytes and
+// pf_create return PF_EINVAL for them): double-precision stochastic-
+// volatility particle learning at 4 items per thread is switched off.
+bool refused_ipt(const pf_config& c, int ipt) {
+    return c.model == PF_SV_PL && c.precision == PF_FP64 && ipt == 4;
+}
 constexpr int64_t kBlock = 256;
 constexpr int64_t kCutMax = 2048;
 
@@ -169,6 +176,7 @@ int pf_autotune(pf_config* cfg, const double* y, int64_t n_obs, void* hip_stream
     };
     // 1. tile size, with the library's default strategy and the tile scan
     for (int ipt : kIpts) {
+        if (refused_ipt(c, ipt)) continue;
         c.items_per_thread = ipt;
         const int rc = consider(c);
         if (rc != PF_OK) return rc;
@@ -225,6 +233,9 @@ int pf_autotune_batch(pf_config* cfgs, int32_t n, const double* y, int64_t n_obs
         return PF_OK;
     };
     for (int ipt : kIpts) {
+        bool refused = false;
+        for (const pf_config& c : cs) refused = refused || refused_ipt(c, ipt);
+        if (refused) continue;
         const int rc = consider(ipt, false);
         if (rc != PF_OK) return rc;
     }

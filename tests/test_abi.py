@@ -77,6 +77,21 @@ def test_workspace_bytes_and_validation(pf):
                          sigma_v2=1, sigma_w2=0.1, x0_var=10)
     with pytest.raises(pf.PFError, match="sorted"):
         pf.workspace_bytes(cfg)
+    # double-precision SV-PL at 4 items per thread is switched off; the
+    # default tile size for it is 1 item per thread
+    svp = dict(x0_mean=-1.0, x0_var=0.1, prior_mean=[-0.05, 0.95], prior_prec=[1.0, 0.0, 1.0],
+               a_s=2.0, d_s=0.04)
+    off = pf.make_config("sv_pl", 1 << 14, 1, scheme=pf.SYSTEMATIC, precision=pf.FP64,
+                         items_per_thread=4, **svp)
+    with pytest.raises(pf.PFError, match="switched off"):
+        pf.workspace_bytes(off)
+    for ipt in (0, 1, 2, 8):
+        ok = pf.make_config("sv_pl", 1 << 14, 1, scheme=pf.SYSTEMATIC, precision=pf.FP64,
+                            items_per_thread=ipt, **svp)
+        assert pf.workspace_bytes(ok) > 0
+    f32 = pf.make_config("sv_pl", 1 << 14, 1, scheme=pf.SYSTEMATIC, precision=pf.FP32,
+                         items_per_thread=4, **svp)
+    assert pf.workspace_bytes(f32) > 0
     # sorted multinomial is switched off: refused with a message that says so
     sm = pf.make_config("ll_pf", 1 << 16, 1, scheme=pf.SORTED_MULTINOMIAL, sigma_v2=1,
                         sigma_w2=0.1, x0_var=10)
