@@ -67,6 +67,8 @@ CASES = [
     ("ll_pl", 16 * 1024, "stratified", "merge", 4, 8, "tiles"),
     ("ll_pl", 16 * 1024 + 1, "stratified", "merge", 4, 8, "tiles"),
     ("sv_pl", 16 * 1024, "systematic", "merge", 8, 8, "tiles"),
+    ("ll_pf", 16 * 1024, "stratified", "merge", 4, 8, "tiles"),
+    ("sv_pf", 16 * 1024 + 3, "systematic", "merge", 4, 8, "tiles"),
     # double-precision SV-PL at 4 items per thread: switched off (refused)
     pytest.param("sv_pl", 16 * 1024, "systematic", "merge", 4, 8, "tiles", marks=SV_PL_FP64_IPT4_OFF),
     pytest.param("sv_pl", 8 * 1024, "systematic", "merge", 4, 8, "lookback", marks=SV_PL_FP64_IPT4_OFF),
