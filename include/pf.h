@@ -88,15 +88,25 @@ enum pf_precision { PF_FP32 = 0, PF_FP64 = 1 };
 
 /* How the inverse CDF a_j = min{k : q(k) >= u_j} is found (Section 3.2).
  * Every strategy returns the same ancestors for the same CDF and uniforms.
- *   PF_SEARCH_AUTO:     library choice (cut-point when the CDF fits one
- *                       work-group's LDS window, merge for sorted uniforms,
- *                       bisection otherwise).
+ *   PF_SEARCH_AUTO:     library choice (merge for sorted uniforms; for
+ *                       multinomial uniforms the cut-point method, except
+ *                       that a CDF of 2049 to 512 x items_per_thread
+ *                       entries, which fits one LDS window but not the LDS
+ *                       cut-point table, merges).
  *   PF_SEARCH_BINARY:   bisection per uniform.
  *   PF_SEARCH_CUTPOINT: the paper's parallel cut-point method: table
  *                       I_k = min{i : q(i) > (k-1)/N} built by the
  *                       parallelized cut-point search, then a climb from
  *                       I_{ceil(N u)}; the climb is bounded, falling back
- *                       to bisection above the start point.
+ *                       to bisection above the start point.  Up to
+ *                       min(2048, 512 x items_per_thread) particles the
+ *                       table is built in each work-group's LDS; above, it
+ *                       lives in the workspace (4 bytes per particle) and
+ *                       is built by a launch of its own after each
+ *                       weighting, from an upper envelope of ceil(N q(i))
+ *                       that keeps every start at or below the answer
+ *                       (needs the default tile scan, not
+ *                       PF_FLAG_LOOKBACK_SCAN).
  *   PF_SEARCH_MERGE:    work-group cooperative merge of sorted uniforms
  *                       against the CDF staged in LDS. */
 enum pf_strategy {

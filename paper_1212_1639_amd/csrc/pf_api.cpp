@@ -21,8 +21,11 @@ hipError_t launch_scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t 
 hipError_t launch_spacings(int ipt, uint64_t seed, uint32_t t, int64_t n, int32_t num_tiles,
                            double* aggE, TileAB* abE, Totals* totE, double* chunk, hipStream_t s);
 int32_t scan_chunks(int32_t num_tiles);
-hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int32_t* base,
-                        int32_t n_filters, BatchState* bs, int grid, hipStream_t s);
+hipError_t launch_cut_table(bool fp64, const void* c, const TileAB* ab, int64_t n, int32_t ts,
+                            int32_t tiles, int32_t* table, hipStream_t s);
+hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int2* tile_map,
+                        int32_t capacity, BatchState* bs, int grid, hipStream_t s);
+hipError_t launch_batch_map(const int32_t* base, int32_t n_filters, int2* tile_map, hipStream_t s);
 int batch_grid(int model, bool fp64, int ipt);
 hipError_t launch_moments(int model, const double* partials, int32_t num_tiles, int64_t n,
                           int32_t weighted, uint32_t t, const ModelParams& p, DevState* st,
@@ -104,9 +107,10 @@ struct Layout {
     int ipt = 0, ts = 0, num_tiles = 0, fields = 0, rsz = 0, strategy = 0;
     int64_t pitch = 0;
     size_t rec[2], c[2], samp[2], tiles[2], tot[2], status, state, partials, anc, agg, ab, hint,
-        chunk, aggE, abE, totE, total;
+        chunk, aggE, abE, totE, cut, total;
     bool spacings = false;  // sorted multinomial: the exponential spacings' tile scan
     bool lookback = false;
+    bool cut_global = false;  // cut-point table in device memory (CDF larger than LDS)
 };
 
 bool finite_all(std::initializer_list<double> v) {
@@ -180,14 +184,17 @@ int plan(const pf_config* c, Layout* L) {
     int strat = c->strategy;
     if (strat == PF_SEARCH_AUTO) {
         if (c->scheme == PF_MULTINOMIAL)
-            strat = n <= cut_max ? PF_SEARCH_CUTPOINT : (n <= win ? PF_SEARCH_MERGE : PF_SEARCH_BINARY);
+            strat = n <= cut_max ? PF_SEARCH_CUTPOINT : (n <= win ? PF_SEARCH_MERGE : PF_SEARCH_CUTPOINT);
         else
             strat = PF_SEARCH_MERGE;
     }
-    if (strat == PF_SEARCH_CUTPOINT && n > cut_max)
-        return fail(PF_EINVAL, "the fused cut-point search builds its table in LDS and needs "
-                               "N <= min(2048, 2 * 256 * items_per_thread); use "
-                               "PF_SEARCH_BINARY or PF_SEARCH_MERGE (or pf_debug_search)");
+    // above one LDS window the cut-point table lives in device memory and is
+    // built by its own launch after each weighting (tile-scan form only)
+    L->cut_global = strat == PF_SEARCH_CUTPOINT && n > cut_max;
+    if (L->cut_global && (c->flags & PF_FLAG_LOOKBACK_SCAN))
+        return fail(PF_EINVAL, "the cut-point search above min(2048, 2 * 256 * items_per_thread) "
+                               "particles builds its table from the tile scan's output; "
+                               "PF_FLAG_LOOKBACK_SCAN is not available with it");
     if (strat == PF_SEARCH_MERGE && c->scheme == PF_MULTINOMIAL && n > win)
         return fail(PF_EINVAL, "the merge search needs sorted uniforms (stratified or systematic) "
                                "when N exceeds one LDS window");
@@ -218,6 +225,7 @@ int plan(const pf_config* c, Layout* L) {
     L->aggE = L->spacings ? take(sizeof(double) * 2 * L->num_tiles) : 0;
     L->abE = L->spacings ? take(sizeof(pf::TileAB) * L->num_tiles) : 0;
     L->totE = L->spacings ? take(sizeof(pf::Totals)) : 0;
+    L->cut = L->cut_global ? take(sizeof(int32_t) * static_cast<size_t>(n)) : 0;
     L->lookback = (c->flags & PF_FLAG_LOOKBACK_SCAN) != 0;
     L->total = off;
     return PF_OK;
@@ -303,12 +311,14 @@ struct pf_filter {
         a.anc_out = (cfg.flags & PF_FLAG_KEEP_ANCESTORS) ? at<int32_t>(L.anc) : nullptr;
         a.scan = L.lookback ? pf::kScanLookback : pf::kScanTiles;
         a.ts = L.ts;
+        a.rsz = L.rsz;
         a.ab_out = at<pf::TileAB>(L.ab);
         a.hint_out = at<int32_t>(L.hint);
         a.ab_in = at<pf::TileAB>(L.ab);
         a.hint_in = at<int32_t>(L.hint);
         a.agg_out = at<double>(L.agg);
         a.abE = L.spacings ? at<pf::TileAB>(L.abE) : nullptr;
+        a.cut_in = L.cut_global ? at<int32_t>(L.cut) : nullptr;
         a.p = mp;
         return a;
     }
@@ -409,6 +419,12 @@ struct pf_filter {
                                       at<double>(L.chunk), pos, stream);
             if (e != hipSuccess) return hip_fail(e, "tile scan launch");
         }
+        if ((a.flags & pf::kWeight) && L.cut_global) {
+            // the cut-point table of the CDF this launch weighed
+            e = pf::launch_cut_table(cfg.precision == PF_FP64, a.c_out, at<pf::TileAB>(L.ab),
+                                     cfg.n_particles, L.ts, L.num_tiles, at<int32_t>(L.cut), stream);
+            if (e != hipSuccess) return hip_fail(e, "cut-point table launch");
+        }
         return PF_OK;
     }
 
@@ -431,12 +447,19 @@ struct pf_batch {
     uint64_t issued = 0;          // steps queued so far (the device counter follows)
     pf::StepArgs* d_descs = nullptr;
     int32_t* d_base = nullptr;
+    int2* d_map = nullptr;        // global tile -> (member, member's tile)
+    int64_t map_cap = 0;          // tiles d_map holds
     pf::BatchState* d_state = nullptr;
     pf::StepArgs* h_stage = nullptr;  // pinned staging of the ring
     std::vector<hipEvent_t> slot_copied;  // slot's staging copy has completed
     // pinned staging of membership updates: kMemberSlots blocks of
-    // (capacity + 1) tile offsets followed by the member count
+    // (capacity + 1) tile offsets followed by a MemberTail
     static constexpr int kMemberSlots = 4;
+    struct MemberTail {
+        int32_t n_filters, capacity;
+        int64_t total_tiles;
+    };
+    size_t member_block_ints() const { return static_cast<size_t>(capacity) + 1 + 6; }
     int32_t* h_member = nullptr;
     hipEvent_t member_copied[kMemberSlots] = {};
     int member_next = 0;
@@ -743,19 +766,40 @@ int pf_batch_update(pf_batch* b, pf_filter* const* filters, int32_t n) {
             return fail(PF_EINVAL, "too many tiles in one batch");
         base[i + 1] = base[i] + filters[i]->L.num_tiles;
     }
+    hipError_t e = hipSuccess;
+    if (base[n] > b->map_cap) {
+        // a larger tile map: steps already queued still read the old one,
+        // and the captured graph holds its address (captured again below)
+        e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, "pf_batch_update synchronise");
+        if (b->exec) {
+            hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->d_map) hipFree(b->d_map);
+        b->d_map = nullptr;
+        b->map_cap = 0;
+        const int64_t cap = std::max<int64_t>(base[n], 2 * static_cast<int64_t>(base[n] / 2 + 512));
+        e = hipMalloc(reinterpret_cast<void**>(&b->d_map), sizeof(int2) * static_cast<size_t>(cap));
+        if (e != hipSuccess) return fail(PF_ENOMEM, "pf_batch_update: hipMalloc of the tile map failed");
+        b->map_cap = cap;
+    }
     // a pinned block whose previous copy has completed (kMemberSlots updates ago)
     const int k = b->member_next;
     b->member_next = (k + 1) % pf_batch::kMemberSlots;
-    hipError_t e = hipEventSynchronize(b->member_copied[k]);
+    e = hipEventSynchronize(b->member_copied[k]);
     if (e != hipSuccess) return hip_fail(e, "pf_batch_update wait");
-    int32_t* blk = b->h_member + static_cast<size_t>(k) * (b->capacity + 2);
+    int32_t* blk = b->h_member + static_cast<size_t>(k) * b->member_block_ints();
     std::memcpy(blk, base.data(), sizeof(int32_t) * (n + 1));
-    blk[b->capacity + 1] = n;
+    const pf_batch::MemberTail tail{n, b->capacity, base[n]};
+    int32_t* tail_at = blk + b->capacity + 2;
+    std::memcpy(tail_at, &tail, sizeof(tail));
     e = hipMemcpyAsync(b->d_base, blk, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&b->d_state->n_filters, blk + b->capacity + 1, sizeof(int32_t),
-                           hipMemcpyHostToDevice, b->stream);
+        e = hipMemcpyAsync(&b->d_state->n_filters, tail_at, sizeof(tail), hipMemcpyHostToDevice,
+                           b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->member_copied[k], b->stream);
+    if (e == hipSuccess) e = pf::launch_batch_map(b->d_base, n, b->d_map, b->stream);
     if (e != hipSuccess) return hip_fail(e, "pf_batch_update copy");
     b->fs.assign(filters, filters + n);
     b->total_tiles = base[n];
@@ -789,7 +833,7 @@ int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t capacity, int3
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_stage), ring_bytes, 0);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&b->h_member),
-                          sizeof(int32_t) * pf_batch::kMemberSlots * (capacity + 2), 0);
+                          sizeof(int32_t) * pf_batch::kMemberSlots * b->member_block_ints(), 0);
     b->slot_copied.assign(ring, nullptr);
     for (int32_t i = 0; i < ring && e == hipSuccess; ++i)
         e = hipEventCreateWithFlags(&b->slot_copied[i], hipEventDisableTiming);
@@ -842,7 +886,7 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = pf::launch_batch(b->model, b->fp64, b->ipt, b->d_descs, b->d_base,
+            hipError_t le = pf::launch_batch(b->model, b->fp64, b->ipt, b->d_descs, b->d_map,
                                              b->capacity, b->d_state, b->grid, cs);
             e = hipStreamEndCapture(cs, &g);
             if (le != hipSuccess) e = le;
@@ -909,6 +953,7 @@ int pf_batch_destroy(pf_batch* b) {
     if (b->h_member) hipHostFree(b->h_member);
     if (b->d_descs) hipFree(b->d_descs);
     if (b->d_base) hipFree(b->d_base);
+    if (b->d_map) hipFree(b->d_map);
     if (b->d_state) hipFree(b->d_state);
     delete b;
     if (e != hipSuccess) return hip_fail(e, "pf_batch_destroy synchronise");

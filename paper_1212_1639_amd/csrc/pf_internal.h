@@ -109,6 +109,8 @@ struct StepArgs {
     int32_t flags;       // StepFlags
     int32_t scan;        // Scan
     int32_t ts;          // particles per tile
+    int32_t rsz;         // bytes per record element (4 or 8)
+    int32_t pad0;
     uint32_t t;          // time index of this step's draws (1-based)
     uint32_t epoch;      // tag of this launch's look-back words (never 0)
     uint64_t seed;
@@ -135,6 +137,8 @@ struct StepArgs {
     DevState* st;
     double* partials;
     int32_t* anc_out;    // ancestors of this step (NULL: not kept)
+    const int32_t* cut_in;      // cut-point table I of the previous CDF (global
+                                //   cut-point search; NULL otherwise)
     ModelParams p;
 };
 
@@ -146,7 +150,8 @@ struct BatchState {
     uint32_t ring;      // argument blocks in the ring (steps that can be queued)
     int32_t n_filters;  // current members (argument blocks hold `capacity` entries)
     int32_t capacity;
-    uint64_t pad[4];
+    int64_t total_tiles;  // tiles of all current members
+    uint64_t pad[3];
 };
 
 }  // namespace pf

@@ -377,6 +377,25 @@ __device__ __forceinline__ int cutpoint_draw(const double* s_q, const int* s_cut
     return k;
 }
 
+// Cut-point draw against a table in device memory (the parallelized
+// cut-point method of Section 3.2 for CDFs larger than one LDS window):
+// start at I_{ceil(n u)}, which the table's construction keeps at or below
+// the answer, and climb; after 16 climbs, bisection above the current
+// point.  A start whose predecessor already reaches u (possible only through
+// rounding where two tiles meet) falls back to bisection below it.
+template <typename R>
+__device__ __forceinline__ int64_t cut_draw_global(const PrevCdf<R>& P, G<const int32_t>* table,
+                                                   double u) {
+    const int64_t n = P.n;
+    const double ce = ceil(static_cast<double>(n) * u);
+    const int64_t e = ce < 1.0 ? 1 : (ce > static_cast<double>(n) ? n : static_cast<int64_t>(ce));
+    int64_t k = min(max(static_cast<int64_t>(table[e - 1]), int64_t(0)), n - 1);
+    if (k > 0 && P.at(k - 1) >= u) return thread_search(P, u, int64_t(0), k - 1);
+    for (int c = 0; c < 16 && k < n - 1 && u > P.at(k); ++c) ++k;
+    if (k < n - 1 && u > P.at(k)) k = thread_search(P, u, k + 1, n - 1);
+    return k;
+}
+
 // Resampling uniform of slot j (Section 3.1), in double precision.  With
 // EXACT the stratum position is divided by N (correctly rounded, as the
 // double-precision reference does); otherwise it is multiplied by 1/N
@@ -673,6 +692,14 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                     }
                     floor = top;
                     __syncthreads();
+                }
+            } else if (strategy == kCutpoint && A.cut_in) {
+                // the paper's cut-point method with the table in device memory
+                G<const int32_t>* table = gp(A.cut_in);
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+                    if (j < n) anc[i] = static_cast<int32_t>(cut_draw_global(P, table, u[i]));
                 }
             } else {
                 // bisection per slot over the tiled CDF
@@ -1066,16 +1093,15 @@ __global__ __launch_bounds__(BLOCK, step_min_blocks<IPT>()) void k_step(StepArgs
 
 // Many filters, one cycle each, in one persistent launch: resident
 // work-groups take global tile numbers from a ticket until all tiles of all
-// filters are done.  Filter f owns global tiles [base[f], base[f+1]); its
-// arguments for step s are descs[(s mod ring) * n_filters + f], where s is
-// the batch's device-side step counter (advanced, and the ticket reset, by
-// k_scan_batch), so the same pair of launches can be replayed step after
-// step.
+// filters are done.  tile_map[g] = (owner filter f, tile of f) for global
+// tile g; filter f's arguments for step s are descs[(s mod ring) * capacity
+// + f], where s is the batch's device-side step counter (advanced, and the
+// ticket reset, by k_scan_batch), so the same pair of launches can be
+// replayed step after step.  Each work-group asks for its next ticket when
+// it starts a tile, so the atomic's round trip overlaps the tile's work.
 template <int MODEL, typename R, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK, batch_min_blocks<IPT>()) void k_step_batch(
-    const StepArgs* __restrict__ descs,
-                                                      const int32_t* __restrict__ base,
-                                                      BatchState* bs) {
+    const StepArgs* __restrict__ descs, const int2* __restrict__ tile_map, BatchState* bs) {
     __shared__ StepSmem<BLOCK, IPT> sm;
     // the batch's state is the same for the whole grid: keep it (and every
     // address derived from it) in scalar registers
@@ -1083,27 +1109,121 @@ __global__ __launch_bounds__(BLOCK, batch_min_blocks<IPT>()) void k_step_batch(
         __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))));
     const int32_t n_filters = static_cast<int32_t>(uniform32(static_cast<uint32_t>(bs->n_filters)));
     if (n_filters <= 0) return;
-    const int64_t total = base[n_filters];
+    const int64_t total = uniform64(bs->total_tiles);
     const uint32_t ring = uniform32(bs->ring);
     const uint32_t capacity = uniform32(static_cast<uint32_t>(bs->capacity));
     const StepArgs* d = descs + (step % ring) * capacity;
-    while (true) {
+    if (threadIdx.x == 0)
+        sm.lo = static_cast<int64_t>(__hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT));
+    __syncthreads();
+    int64_t g = uniform64(sm.lo);
+    while (g < total) {
+        uint64_t next = 0;
         if (threadIdx.x == 0)
-            sm.lo = static_cast<int64_t>(__hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT));
+            next = __hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        const int2 owner = tile_map[g];
+        const int32_t f = static_cast<int32_t>(uniform32(static_cast<uint32_t>(owner.x)));
+        const uint32_t tile = uniform32(static_cast<uint32_t>(owner.y));
+        cycle<MODEL, R, BLOCK, IPT>(d[f], tile, sm);
+        // every wave is past the cycle's last use of the shared fields
         __syncthreads();
-        const int64_t g = uniform64(sm.lo);
+        if (threadIdx.x == 0) sm.lo = static_cast<int64_t>(next);
         __syncthreads();
-        if (g >= total) break;
-        // owner of global tile g: largest f with base[f] <= g
-        int lo = 0, hi = n_filters - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (base[mid] <= g) lo = mid; else hi = mid - 1;
-        }
-        cycle<MODEL, R, BLOCK, IPT>(d[lo], static_cast<uint32_t>(g - base[lo]), sm);
-        __syncthreads();
+        g = uniform64(sm.lo);
     }
+}
+
+// tile_map[base[f] + k] = (f, k) for every tile k of member f (one
+// work-group per member).
+__global__ __launch_bounds__(256) void k_batch_map(const int32_t* __restrict__ base,
+                                                   int32_t n_filters, int2* __restrict__ tile_map) {
+    const int32_t f = blockIdx.x;
+    if (f >= n_filters) return;
+    const int32_t b0 = base[f], b1 = base[f + 1];
+    for (int32_t k = threadIdx.x; b0 + k < b1; k += blockDim.x) tile_map[b0 + k] = make_int2(f, k);
+}
+
+// ------------------------------------------------------------ cut-point table
+// The parallelized cut-point search of Section 3.2 over the tiled CDF
+// q(k) = A_b + c[k] B_b: entry e (1-based) of the table receives
+// I_e = min{j : L'_j >= e}, where L'_j is an upper envelope of
+// L_j = ceil(n q(j)) that is non-decreasing in j.  Inside a tile q is
+// non-decreasing, so L' = max(L, F_b) there, with the tile's floor
+// F_b = ceil(n A_b) + 1 (F_0 = 0) bounding every L of the tiles before it
+// (their q are at most A_b up to a few ulps); a tile's last element takes
+// F_{b+1} and the CDF's last element n.  Since L' >= L, I_e never exceeds
+// the answer min{k : q(k) >= u} of any u with ceil(n u) = e, so a climb
+// from it is exact; since L' is non-decreasing, element j owns exactly the
+// entries (L'_{j-1}, L'_j] and writes its index there, and every entry is
+// written once.  A thread writes at most kCutRun entries of its own range;
+// the rest of a longer range (a heavy particle) is filled by its whole
+// work-group.
+constexpr int kCutRun = 32;
+
+template <typename R>
+struct CutEnvelope {
+    const R* c;
+    const TileAB* ab;
+    int64_t n;
+    int32_t ts, tiles;
+    // ceil(x) as an entry count in [0, n] (0 for NaN)
+    __device__ __forceinline__ int64_t count(double x) const {
+        return x >= 1.0 ? (x >= static_cast<double>(n) ? n : static_cast<int64_t>(x)) : 0;
+    }
+    __device__ __forceinline__ int64_t floor_of(int64_t b) const {
+        return b <= 0 ? 0 : count(ceil(static_cast<double>(n) * ab[b].a) + 1.0);
+    }
+    // L'_k, with L'_{-1} = 0
+    __device__ __forceinline__ int64_t at(int64_t k) const {
+        if (k < 0) return 0;
+        if (k >= n - 1) return n;
+        const int64_t b = k / ts;
+        if (k == (b + 1) * ts - 1) return floor_of(b + 1);
+        const TileAB t = ab[b];
+        const double L = ceil(static_cast<double>(n) * fma(static_cast<double>(c[k]), t.b, t.a));
+        return max(count(L), floor_of(b));
+    }
+};
+
+// Entries of the elements j0 .. j0 + NT - 1 (one per thread) written by a
+// work-group of NT threads; s_lo, s_hi, s_j hold NT entries, *s_count one.
+template <int NT, typename R>
+__device__ __forceinline__ void cut_table_block(const CutEnvelope<R>& E, int64_t j0,
+                                                int32_t* __restrict__ table, int64_t* s_lo,
+                                                int64_t* s_hi, int32_t* s_j, int* s_count) {
+    const int tid = threadIdx.x;
+    if (tid == 0) *s_count = 0;
+    __syncthreads();
+    const int64_t j = j0 + tid;
+    if (j < E.n) {
+        const int64_t lo = E.at(j - 1), hi = E.at(j);
+        const int64_t own = min(hi, lo + kCutRun);
+        for (int64_t e = lo; e < own; ++e) table[e] = static_cast<int32_t>(j);
+        if (hi > own) {
+            const int slot = atomicAdd(s_count, 1);
+            s_lo[slot] = own;
+            s_hi[slot] = hi;
+            s_j[slot] = static_cast<int32_t>(j);
+        }
+    }
+    __syncthreads();
+    const int count = *s_count;
+    for (int q = 0; q < count; ++q) {
+        const int32_t v = s_j[q];
+        for (int64_t e = s_lo[q] + tid; e < s_hi[q]; e += NT) table[e] = v;
+    }
+    __syncthreads();
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cut_table(CutEnvelope<R> E, int32_t* __restrict__ table) {
+    __shared__ int64_t s_lo[256], s_hi[256];
+    __shared__ int32_t s_j[256];
+    __shared__ int s_count;
+    cut_table_block<256>(E, static_cast<int64_t>(blockIdx.x) * 256, table, s_lo, s_hi, s_j,
+                         &s_count);
 }
 
 // ------------------------------------------------------------ tile scan
@@ -1547,11 +1667,31 @@ __global__ __launch_bounds__(kTileScanBlock) void k_scan_batch(const StepArgs* _
     const uint64_t step = __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int32_t n_filters = bs->n_filters;
     const StepArgs* d = descs + (step % static_cast<uint64_t>(bs->ring)) * bs->capacity;
+    __shared__ int64_t s_lo[kTileScanBlock], s_hi[kTileScanBlock];
+    __shared__ int32_t s_j[kTileScanBlock];
+    __shared__ int s_count;
     for (int32_t f = blockIdx.x; f < n_filters; f += gridDim.x) {
         const StepArgs& A = d[f];
         if ((A.flags & kWeight) && !(A.flags & kFusedScan))
             scan_tiles(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out, A.tot_out, A.st);
         __syncthreads();
+        if ((A.flags & kWeight) && A.cut_in) {
+            // the cut-point table of the CDF just weighed (the next step's
+            // cut_in), built by this work-group
+            int32_t* table = const_cast<int32_t*>(A.cut_in);
+            const bool fp64 = A.rsz == 8;
+            for (int64_t j0 = 0; j0 < A.n; j0 += kTileScanBlock) {
+                if (fp64) {
+                    const CutEnvelope<double> E{static_cast<const double*>(A.c_out), A.ab_out, A.n,
+                                                A.ts, A.num_tiles};
+                    cut_table_block<kTileScanBlock>(E, j0, table, s_lo, s_hi, s_j, &s_count);
+                } else {
+                    const CutEnvelope<float> E{static_cast<const float*>(A.c_out), A.ab_out, A.n,
+                                               A.ts, A.num_tiles};
+                    cut_table_block<kTileScanBlock>(E, j0, table, s_lo, s_hi, s_j, &s_count);
+                }
+            }
+        }
     }
     if (threadIdx.x == 0) {
         const uint32_t dn = __hip_atomic_fetch_add(&bs->done, 1u, __ATOMIC_RELAXED,
@@ -1844,45 +1984,50 @@ hipError_t launch_step(int model, bool fp64, int ipt, const StepArgs& a, int gri
 }
 
 template <int MODEL, typename R, int IPT>
-static hipError_t launch_batch_t(const StepArgs* descs, const int32_t* base, int32_t n_filters,
-                                 BatchState* bs, int grid, hipStream_t s) {
-    (void)n_filters;
-    hipLaunchKernelGGL((k_step_batch<MODEL, R, 256, IPT>), dim3(grid), dim3(256), 0, s, descs, base,
-                       bs);
+static hipError_t launch_batch_t(const StepArgs* descs, const int2* tile_map, BatchState* bs,
+                                 int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_step_batch<MODEL, R, 256, IPT>), dim3(grid), dim3(256), 0, s, descs,
+                       tile_map, bs);
     return hipGetLastError();
 }
 
 template <int MODEL, typename R>
-static hipError_t launch_batch_m(int ipt, const StepArgs* descs, const int32_t* base,
-                                 int32_t n_filters, BatchState* bs, int grid, hipStream_t s) {
+static hipError_t launch_batch_m(int ipt, const StepArgs* descs, const int2* tile_map,
+                                 BatchState* bs, int grid, hipStream_t s) {
     switch (ipt) {
-    case 1: return launch_batch_t<MODEL, R, 1>(descs, base, n_filters, bs, grid, s);
-    case 2: return launch_batch_t<MODEL, R, 2>(descs, base, n_filters, bs, grid, s);
-    case 4: return launch_batch_t<MODEL, R, 4>(descs, base, n_filters, bs, grid, s);
-    case 8: return launch_batch_t<MODEL, R, 8>(descs, base, n_filters, bs, grid, s);
+    case 1: return launch_batch_t<MODEL, R, 1>(descs, tile_map, bs, grid, s);
+    case 2: return launch_batch_t<MODEL, R, 2>(descs, tile_map, bs, grid, s);
+    case 4: return launch_batch_t<MODEL, R, 4>(descs, tile_map, bs, grid, s);
+    case 8: return launch_batch_t<MODEL, R, 8>(descs, tile_map, bs, grid, s);
     }
     return hipErrorInvalidValue;
 }
 
 // One batched cycle: the persistent step kernel over all filters' tiles,
-// then one scan work-group per filter.
-hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int32_t* base,
-                        int32_t n_filters, BatchState* bs, int grid, hipStream_t s) {
+// then the filters' tile scans (capacity bounds the scan grid).
+hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int2* tile_map,
+                        int32_t capacity, BatchState* bs, int grid, hipStream_t s) {
     hipError_t e = hipErrorInvalidValue;
     switch (model) {
-    case kLLPF: e = fp64 ? launch_batch_m<kLLPF, double>(ipt, descs, base, n_filters, bs, grid, s)
-                         : launch_batch_m<kLLPF, float>(ipt, descs, base, n_filters, bs, grid, s); break;
-    case kLLPL: e = fp64 ? launch_batch_m<kLLPL, double>(ipt, descs, base, n_filters, bs, grid, s)
-                         : launch_batch_m<kLLPL, float>(ipt, descs, base, n_filters, bs, grid, s); break;
-    case kSVPF: e = fp64 ? launch_batch_m<kSVPF, double>(ipt, descs, base, n_filters, bs, grid, s)
-                         : launch_batch_m<kSVPF, float>(ipt, descs, base, n_filters, bs, grid, s); break;
-    case kSVPL: e = fp64 ? launch_batch_m<kSVPL, double>(ipt, descs, base, n_filters, bs, grid, s)
-                         : launch_batch_m<kSVPL, float>(ipt, descs, base, n_filters, bs, grid, s); break;
+    case kLLPF: e = fp64 ? launch_batch_m<kLLPF, double>(ipt, descs, tile_map, bs, grid, s)
+                         : launch_batch_m<kLLPF, float>(ipt, descs, tile_map, bs, grid, s); break;
+    case kLLPL: e = fp64 ? launch_batch_m<kLLPL, double>(ipt, descs, tile_map, bs, grid, s)
+                         : launch_batch_m<kLLPL, float>(ipt, descs, tile_map, bs, grid, s); break;
+    case kSVPF: e = fp64 ? launch_batch_m<kSVPF, double>(ipt, descs, tile_map, bs, grid, s)
+                         : launch_batch_m<kSVPF, float>(ipt, descs, tile_map, bs, grid, s); break;
+    case kSVPL: e = fp64 ? launch_batch_m<kSVPL, double>(ipt, descs, tile_map, bs, grid, s)
+                         : launch_batch_m<kSVPL, float>(ipt, descs, tile_map, bs, grid, s); break;
     }
     if (e != hipSuccess) return e;
-    // n_filters here is the batch's capacity: the scan grid covers it
-    const int sgrid = n_filters < 256 ? (n_filters > 0 ? n_filters : 1) : 256;
+    const int sgrid = capacity < 256 ? (capacity > 0 ? capacity : 1) : 256;
     hipLaunchKernelGGL(k_scan_batch, dim3(sgrid), dim3(kTileScanBlock), 0, s, descs, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_map(const int32_t* base, int32_t n_filters, int2* tile_map,
+                            hipStream_t s) {
+    if (n_filters <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_map, dim3(n_filters), dim3(256), 0, s, base, n_filters, tile_map);
     return hipGetLastError();
 }
 
@@ -1965,6 +2110,19 @@ hipError_t launch_moments(int model, const double* partials, int32_t num_tiles, 
     case kSVPF: hipLaunchKernelGGL(k_moments<kSVPF>, dim3(1), dim3(256), 0, s, partials, num_tiles, n, weighted, t, p, st); break;
     case kSVPL: hipLaunchKernelGGL(k_moments<kSVPL>, dim3(1), dim3(256), 0, s, partials, num_tiles, n, weighted, t, p, st); break;
     default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_table(bool fp64, const void* c, const TileAB* ab, int64_t n, int32_t ts,
+                            int32_t tiles, int32_t* table, hipStream_t s) {
+    const int64_t grid = (n + 255) / 256;
+    if (fp64) {
+        CutEnvelope<double> E{static_cast<const double*>(c), ab, n, ts, tiles};
+        hipLaunchKernelGGL(k_cut_table<double>, dim3(grid), dim3(256), 0, s, E, table);
+    } else {
+        CutEnvelope<float> E{static_cast<const float*>(c), ab, n, ts, tiles};
+        hipLaunchKernelGGL(k_cut_table<float>, dim3(grid), dim3(256), 0, s, E, table);
     }
     return hipGetLastError();
 }

@@ -52,7 +52,9 @@ std::vector<int32_t> strategies(int32_t scheme, int64_t n, int ipt) {
     const int64_t win = 2 * kBlock * ipt;
     const int64_t cut = win < kCutMax ? win : kCutMax;
     std::vector<int32_t> s;
-    if (n <= cut) s.push_back(PF_SEARCH_CUTPOINT);
+    // the cut-point search: in LDS up to `cut`, with its table in device
+    // memory above (multinomial uniforms only: sorted ones merge)
+    if (n <= cut || scheme == PF_MULTINOMIAL) s.push_back(PF_SEARCH_CUTPOINT);
     if (scheme != PF_MULTINOMIAL || n <= win) s.push_back(PF_SEARCH_MERGE);
     s.push_back(PF_SEARCH_BINARY);
     return s;
@@ -190,9 +192,13 @@ int pf_autotune(pf_config* cfg, const double* y, int64_t n_obs, void* hip_stream
         if (rc != PF_OK) return rc;
     }
     // 3. scan: the decoupled look-back instead of the tile scan (sorted
-    //    multinomial resampling needs the tile scan)
+    //    multinomial resampling and the cut-point table in device memory
+    //    need the tile scan)
     c.strategy = best.strategy;
-    if (c.scheme != PF_SORTED_MULTINOMIAL) {
+    const int64_t win = 2 * kBlock * best.ipt;
+    const bool cut_global = best.strategy == PF_SEARCH_CUTPOINT &&
+                            c.n_particles > (win < kCutMax ? win : kCutMax);
+    if (c.scheme != PF_SORTED_MULTINOMIAL && !cut_global) {
         c.flags |= PF_FLAG_LOOKBACK_SCAN;
         const int rc = consider(c);
         if (rc != PF_OK) return rc;

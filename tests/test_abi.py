@@ -67,9 +67,19 @@ def test_workspace_bytes_and_validation(pf):
         cfg = pf.make_config(kw.pop("model"), kw.pop("n"), kw.pop("seed"), **kw)
         with pytest.raises(pf.PFError):
             pf.workspace_bytes(cfg)
-    # the fused cut-point table lives in LDS: N above one window is refused
+    # above one LDS window the cut-point table lives in the workspace (one
+    # int32 per particle) and is built from the tile scan, so the look-back
+    # scan is refused with it
+    small = pf.make_config("ll_pf", 2048, 1, strategy=pf.SEARCH_CUTPOINT, items_per_thread=4,
+                           sigma_v2=1, sigma_w2=0.1, x0_var=10)
+    big = pf.make_config("ll_pf", 1 << 16, 1, strategy=pf.SEARCH_CUTPOINT, items_per_thread=4,
+                         sigma_v2=1, sigma_w2=0.1, x0_var=10)
+    binary = pf.make_config("ll_pf", 1 << 16, 1, strategy=pf.SEARCH_BINARY, items_per_thread=4,
+                            sigma_v2=1, sigma_w2=0.1, x0_var=10)
+    assert pf.workspace_bytes(small) > 0
+    assert pf.workspace_bytes(big) >= pf.workspace_bytes(binary) + 4 * (1 << 16)
     cfg = pf.make_config("ll_pf", 1 << 16, 1, strategy=pf.SEARCH_CUTPOINT, sigma_v2=1,
-                         sigma_w2=0.1, x0_var=10)
+                         sigma_w2=0.1, x0_var=10, flags=pf.FLAG_LOOKBACK_SCAN)
     with pytest.raises(pf.PFError, match="cut-point"):
         pf.workspace_bytes(cfg)
     # merge needs sorted uniforms once the CDF exceeds a window

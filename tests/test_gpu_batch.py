@@ -41,6 +41,9 @@ def _state(f):
                                                 ("ll_pf", "multinomial", False),
                                                 ("sv_pf", "stratified", True)])
 def test_batch_equals_alone(pf, model, scheme, fp32):
+    # multinomial members above 512 particles (one tile of 1 item per
+    # thread: the LDS window) use the cut-point table in device memory,
+    # which the batch builds in its scan launch
     sizes = [700, 3000, 256, 5001, 1]
     print(f"batch vs alone {model} sizes={sizes}", flush=True)
     T = 12

@@ -69,6 +69,13 @@ CASES = [
     ("sv_pl", 16 * 1024, "systematic", "merge", 8, 8, "tiles"),
     ("ll_pf", 16 * 1024, "stratified", "merge", 4, 8, "tiles"),
     ("sv_pf", 16 * 1024 + 3, "systematic", "merge", 4, 8, "tiles"),
+    # the cut-point method with its table in device memory (multinomial
+    # above one LDS window): built after each weighting, then a bounded climb
+    ("ll_pf", 3000, "multinomial", "cutpoint", 1, 20, "tiles"),
+    ("ll_pl", 20000, "multinomial", "auto", 4, 12, "tiles"),
+    ("sv_pf", 16 * 1024 + 1, "multinomial", "cutpoint", 4, 8, "tiles"),
+    ("sv_pl", 5000, "multinomial", "auto", 2, 12, "tiles"),
+    ("ll_pf", 9000, "multinomial", "cutpoint", 8, 10, "tiles"),
     # double-precision SV-PL at 4 items per thread: switched off (refused)
     pytest.param("sv_pl", 16 * 1024, "systematic", "merge", 4, 8, "tiles", marks=SV_PL_FP64_IPT4_OFF),
     pytest.param("sv_pl", 8 * 1024, "systematic", "merge", 4, 8, "lookback", marks=SV_PL_FP64_IPT4_OFF),
@@ -250,6 +257,34 @@ def test_repeat_runs(pf, scan):
         np.testing.assert_array_equal(res[0][1], res[1][1])
     else:
         assert abs(res[0][0] - res[1][0]) < 1e-9
+
+
+def test_cutpoint_table_with_dominant_particles(pf, orc):
+    """The cut-point search in device memory when a few particles carry
+    almost all the weight (Section 3.2's worst case for the table: one
+    particle owns a long run of entries, filled by its whole work-group):
+    an outlying observation, then ordinary ones; ancestors bit-exact and
+    records within 1e-9 of the oracle at every step."""
+    n, T = 60000, 8
+    print(f"cut-point table, dominant particles n={n}", flush=True)
+    y = C.data("ll_pf", T).copy()
+    y[2] += 6.0   # a jump of 6 observation s.d.: few particles keep weight
+    ocfg = C.oracle_config(orc, "ll_pf", n, 21, "multinomial", fp32=False)
+    ref = orc.run(ocfg, y, dump=True)
+    assert ref["rc"] == 0
+    f = pf.Filter(C.pf_config(pf, "ll_pf", n, 21, "multinomial", fp32=False,
+                              strategy=pf.SEARCH_CUTPOINT, ipt=4))
+    for t in range(1, T + 1):
+        f.step(y[t - 1])
+        rec, anc, tt = f.particles()
+        assert tt == t
+        np.testing.assert_array_equal(anc, ref["anc"][t - 1])
+        np.testing.assert_allclose(rec, ref["state"][t - 1], rtol=1e-9, atol=1e-11)
+        ll = f.loglik()
+        assert abs(ll - ref["loglik"][:t].sum()) < 1e-9 * max(1.0, abs(ll))
+    # the step after the jump resamples from a few ancestors
+    assert np.unique(ref["anc"][3]).size < n // 10
+    f.close()
 
 
 def test_errors(pf):
