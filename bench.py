@@ -14,10 +14,12 @@ graph replay), and the CPU oracle timed on a bounded sample of the same
 workload (one filter per host core for the batched and served workloads).
 
 Workloads (all synthetic; data simulated from the model):
-  ll_pl_2p20  particle learning, local-level model, unknown variances under
-              IG(2, 1) priors, N = 2^20, T = 500, stratified, FP32 (default)
   sv_pl_2p26  particle learning, stochastic volatility, unknown
               (alpha, beta, sigma^2), N = 2^26, T = 1000, systematic, FP32
+              (default; the line also carries the batched-vs-plain figures
+              of ll_pl_batch256 under "batched")
+  ll_pl_2p20  particle learning, local-level model, unknown variances under
+              IG(2, 1) priors, N = 2^20, T = 500, stratified, FP32
   ll_pf_1024  bootstrap filter, local-level model, known variances,
               N = 1024, T = 100, multinomial, FP64
   served_mix  a Poisson stream (200 requests/s for 30 s) of filter requests,
@@ -110,9 +112,13 @@ WORKLOADS = {
                        params=dict(x0_mean=-1.0, x0_var=0.04 / (1 - 0.95**2),
                                    prior_mean=[-0.05, 0.95], prior_prec=[1.0, 0.0, 1.0],
                                    a_s=2.0, d_s=0.04),
-                       # record x + 5 per-particle statistics (4 B each) read + written,
-                       # CDF prefix written then read
-                       bytes_per_particle=2 * 24 + 8),
+                       # the scope table's figure: a record of x + 7 statistics
+                       # (4 B each) read + written, one weight passed across the
+                       # scan (written then read)
+                       bytes_per_particle=2 * 32 + 8,
+                       # what this record layout moves: x + 5 per-particle
+                       # statistics (the shape and L00 are per filter)
+                       record_bytes_per_particle=2 * 24 + 8),
     "ll_pf_1024": dict(model="ll_pf", n=1024, T=100, scheme="multinomial", fp32=False,
                        params=dict(x0_mean=0.0, x0_var=10.0, sigma_v2=1.0, sigma_w2=0.1),
                        bytes_per_particle=2 * 8 + 16),
@@ -292,22 +298,35 @@ def run_paper(args, w, pf, torch):
     print(json.dumps(out), flush=True)
 
 
-def run_batch(args, w, pf, torch):
-    """Batched vs plain stepping of many filters of uneven N."""
+def measure_batch(args, w, pf, torch, K, W, tune=True):
+    """Batched vs plain stepping of many filters of uneven N: the batch's
+    common tile size and search chosen by the library's autotuner (when
+    `tune`), then K full cycles of the batch (one persistent launch per
+    step, replayed from a HIP graph) and the same K cycles with every filter
+    stepped alone, one after the other.  The first observation of each
+    filter (which only weighs) is stepped before the timed region."""
     from paper_1212_1639_amd import inputs
     nf = w["filters"]
     sizes = inputs.batch_sizes(nf, 12, 18, seed=0)
-    K = args.steps or w["T"]
-    W = args.warmup
-    T = max(K, W, 1)
+    T = max(K + 1, W, 3)
     y = np.stack([inputs.local_level(T, seed=f)[0] for f in range(nf)], axis=1)  # (T, nf)
     stream = torch.cuda.Stream()
 
-    def filters():
-        return [pf.Filter(pf.make_config(w["model"], int(n), f, scheme=pf.STRATIFIED,
-                                         precision=pf.FP32, items_per_thread=args.items_per_thread,
-                                         **w["params"]), stream=stream)
+    def configs():
+        return [pf.make_config(w["model"], int(n), f, scheme=pf.STRATIFIED, precision=pf.FP32,
+                               items_per_thread=args.items_per_thread, **w["params"])
                 for f, n in enumerate(sizes)]
+
+    cfgs = configs()
+    tuned = None
+    if tune and not args.items_per_thread:
+        n_obs = min(T, 8)
+        tuned_ms = pf.autotune_batch(cfgs, y[:n_obs], stream=stream)
+        tuned = {"items_per_thread": int(cfgs[0].items_per_thread),
+                 "strategy": int(cfgs[0].strategy), "tuning_ms_per_step": tuned_ms}
+
+    def filters():
+        return [pf.Filter(c, stream=stream) for c in cfgs]
 
     if W > 0:
         warm = filters()
@@ -319,12 +338,13 @@ def run_batch(args, w, pf, torch):
             f.close()
     fs = filters()
     b = pf.Batch(fs, ring=min(K, 256))
+    b.step(y[:1])
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    b.step(y[:K])
+    b.step(y[1:K + 1])
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -335,57 +355,68 @@ def run_batch(args, w, pf, torch):
         f.close()
     # plain: the same filters, each stepped alone, one after the other
     ps = filters()
+    for k, f in enumerate(ps):
+        f.step(y[:1, k])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k, f in enumerate(ps):
-        f.step(y[:K, k])
+        f.step(y[1:K + 1, k])
     torch.cuda.synchronize()
     wall_plain = time.perf_counter() - t0
     lls_plain = [f.loglik() for f in ps]
     for f in ps:
         f.close()
     total = int(sizes.sum())
-    value = total * K / wall
     step_s = ev_ms * 1e-3 / K
     bytes_step = w["bytes_per_particle"] * total
     achieved = bytes_step / step_s / 1e9
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
+    return {
+        "value": total * K / wall,
         "ms_per_step": wall * 1e3 / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "model": w["model"], "filters": nf,
+        "config": {"workload": "ll_pl_batch256", "model": w["model"], "filters": nf,
                    "total_particles": total, "n_min": int(sizes.min()), "n_max": int(sizes.max()),
-                   "T": w["T"], "scheme": w["scheme"], "form": "batched"},
+                   "T": w["T"], "scheme": w["scheme"], "form": "batched",
+                   "items_per_thread": int(cfgs[0].items_per_thread),
+                   "strategy": int(cfgs[0].strategy), "autotuned": tuned is not None},
+        "autotune": tuned,
         "plain": {"value": total * K / wall_plain, "ms_per_step": wall_plain * 1e3 / K},
         "batched_over_plain": wall_plain / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes("ll_pl_batch256"),
                      "kernel": "k_step_batch + k_scan_batch", "kernel_avg_us": step_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_step},
         "batched_equals_plain_loglik": bool(np.array_equal(np.array(lls), np.array(lls_plain))),
+        "sizes": sizes,
+        "y": y,
     }
+
+
+def run_batch(args, w, pf, torch):
+    """The batched workload on its own line."""
+    K = args.steps or w["T"]
+    W = args.warmup
+    r = measure_batch(args, w, pf, torch, K, W)
+    sizes, y = r.pop("sizes"), r.pop("y")
+    out = {"metric": METRIC, "value": r["value"], "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": K, "warmup": W, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    out.update({k: v for k, v in r.items() if k not in ("value", "ms_per_step")})
     if not args.no_cpu_baseline:
-        # the oracle on the filters of the same workload in order, one filter
-        # per host core, for about 15 s
-        import oracle
-        jobs = ((oracle.make_config(oracle.LL_PL, int(n), f, scheme=oracle.STRATIFIED,
-                                    fp32_words=True, **w["params"]), y[:K, f])
-                for f, n in enumerate(sizes))
-        rate, workers, done = oracle_pool_rate(jobs)
-        out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": workers,
-                               "kind": "oracle",
-                               "sample": f"first {done} of {nf} filters, all {K} steps each, one "
-                                         f"filter per worker thread (FP64 C oracle)"}
+        out["cpu_baseline"] = batch_cpu_baseline(w, sizes, y, K)
     print(json.dumps(out), flush=True)
+
+
+def batch_cpu_baseline(w, sizes, y, K):
+    """The oracle on the filters of the batched workload in order, one filter
+    per host core, for about 15 s."""
+    import oracle
+    jobs = ((oracle.make_config(oracle.LL_PL, int(n), f, scheme=oracle.STRATIFIED,
+                                fp32_words=True, **w["params"]), y[1:K + 1, f])
+            for f, n in enumerate(sizes))
+    rate, workers, done = oracle_pool_rate(jobs)
+    return {"value": rate, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {done} of {len(sizes)} filters, {K} steps each, one filter per "
+                      f"worker thread (FP64 C oracle)", "host": host_info()}
 
 
 def data(w, T):
@@ -395,27 +426,79 @@ def data(w, T):
     return inputs.stochastic_volatility(T, seed=0)[0]
 
 
+def host_info():
+    """Host cores (all, and those this process may run on) and CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": model}
+
+
+def synthetic_state(w, n, seed=12345):
+    """Particles after one step, drawn from the model with its true
+    parameters, in the oracle's field layout: the CPU baseline starts from
+    them so that it times full cycles (resample, propagate, weigh) and not
+    the initial draw.  numpy draws; none of the filter's arithmetic."""
+    from paper_1212_1639_amd import inputs
+    rng = np.random.default_rng(seed)
+    m = w["model"]
+    if m == "sv_pl":
+        tr = inputs.SV_TRUTH
+        x0 = tr["mu"] + tr["sigma"] / np.sqrt(1 - tr["phi"] ** 2) * rng.standard_normal(n)
+        x1 = tr["mu"] + tr["phi"] * (x0 - tr["mu"]) + tr["sigma"] * rng.standard_normal(n)
+        # (x, n, S1, S11, Sy, S1y, Syy): the path sums of one transition
+        return np.stack([x1, np.ones(n), x0, x0 * x0, x1, x0 * x1, x1 * x1])
+    if m == "ll_pl":
+        p = w["params"]
+        x = p["x0_mean"] + np.sqrt(p["x0_var"]) * rng.standard_normal(n)
+        bv = np.full(n, p["b_v"])
+        bw = np.full(n, p["b_w"])
+        return np.stack([x, bv, bw, bv / rng.gamma(p["a_v"], size=n),
+                         bw / rng.gamma(p["a_w"], size=n)])
+    p = w["params"]
+    return (p["x0_mean"] + np.sqrt(p["x0_var"]) * rng.standard_normal(n))[None, :]
+
+
 def cpu_baseline(w, y, budget_s=15.0):
-    """The oracle as it stands, sequential (1 thread), on the first few steps
-    of the same workload: enough steps for about `budget_s` seconds."""
+    """The oracle as it stands, sequential (1 thread), timed over full cycles
+    of the same workload from a particle state after step 1 (its
+    initialisation left out): about `budget_s` seconds of steps."""
     import oracle
     model = {"ll_pf": oracle.LL_PF, "ll_pl": oracle.LL_PL, "sv_pf": oracle.SV_PF,
              "sv_pl": oracle.SV_PL}[w["model"]]
     scheme = {"multinomial": oracle.MULTINOMIAL, "stratified": oracle.STRATIFIED,
               "systematic": oracle.SYSTEMATIC}[w["scheme"]]
     n = w["n"]
-    # a short probe sizes the sample
     cfg = oracle.make_config(model, n, 1, scheme=scheme, fp32_words=w["fp32"], **w["params"])
-    t0 = time.perf_counter()
-    oracle.run(cfg, y[:1])
-    per_step = max(time.perf_counter() - t0, 1e-6)
-    steps = int(max(1, min(len(y), budget_s / per_step)))
-    t0 = time.perf_counter()
-    oracle.run(cfg, y[:steps])
-    dt = time.perf_counter() - t0
-    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} of {w['T']} steps at N={n} (sequential FP64 C oracle, "
-                      f"initialisation included)"}
+    s0 = synthetic_state(w, n)
+    oracle.lib()
+    steps, done, dt = 1, 0, 0.0
+    t_all = time.perf_counter()
+    while done < len(y) - 1:
+        k = min(steps, len(y) - 1 - done)
+        t0 = time.perf_counter()
+        oracle.run(cfg, y[1 + done:1 + done + k], state0=s0, t0=1 + done, y_prev=y[done])
+        dt += time.perf_counter() - t0
+        done += k
+        left = budget_s - (time.perf_counter() - t_all)
+        if left < dt / done:
+            break
+        # the next batch of steps fits the rest of the budget
+        steps = max(1, int(left / (dt / done)))
+    return {"value": n * done / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} full cycles at N={n} (sequential FP64 C oracle from a synthetic "
+                      f"particle state after step 1, its initialisation not timed)",
+            "host": host_info()}
 
 
 def main():
@@ -423,8 +506,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the workload's T)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ll_pl_2p20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="sv_pl_2p26", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="sv_pl_2p26: leave out the batched-vs-plain figures of ll_pl_batch256")
     ap.add_argument("--items-per-thread", type=int, default=0)
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="served_mix: device memory budget (default 80%% of free memory)")
@@ -470,7 +555,7 @@ def main():
         return
     K = args.steps or w["T"]
     W = args.warmup
-    y = data(w, max(K, W, 1))
+    y = data(w, max(K + 1, W, 2))
     scheme = {"multinomial": pf.MULTINOMIAL, "stratified": pf.STRATIFIED,
               "systematic": pf.SYSTEMATIC}[w["scheme"]]
     cfg = pf.make_config(w["model"], w["n"], 1, scheme=scheme,
@@ -487,13 +572,17 @@ def main():
         del warm
 
     f = pf.Filter(cfg, stream=stream)
+    # the first observation only weighs (particle learning on the local-level
+    # model) or has nothing to resample (the other models): it is stepped
+    # before the timed region, so that every timed step is a full cycle
+    f.step(y[:1])
     # one cycle launch in TIMING_EVERY is bracketed by a pair of HIP events
     # on the filter's stream (the events' own cost then stays out of the
     # other launches and of the throughput)
     f.timing_start(K, TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    f.step(y[:K])
+    f.step(y[1:K + 1])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
@@ -508,6 +597,17 @@ def main():
     kern_s = kern_ms * 1e-3 / max(1, launches)
     bytes_launch = w["bytes_per_particle"] * n
     achieved = bytes_launch / kern_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(args.workload),
+            "kernel": "k_step", "kernel_avg_us": kern_s * 1e6, "kernel_launches_timed": launches,
+            "bytes_per_particle": w["bytes_per_particle"],
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "valu_issue": valu_issue(args.workload)}
+    rb = w.get("record_bytes_per_particle")
+    if rb:
+        # the bytes this record layout moves (two statistics are per filter)
+        roof["record_bytes_per_particle"] = rb
+        roof["record_frac"] = rb * n / kern_s / 1e9 / HBM_PEAK_GBS
     out = {
         "metric": METRIC,
         "value": value,
@@ -522,16 +622,19 @@ def main():
         "dtype": "f32" if w["fp32"] else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "model": w["model"], "n_particles": n,
-                   "T": w["T"], "scheme": w["scheme"], "form": "plain"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes(args.workload),
-                     "kernel": "k_step", "kernel_avg_us": kern_s * 1e6, "kernel_launches_timed": launches,
-                     "algorithmic_bytes_per_launch": bytes_launch,
-                     "valu_issue": valu_issue(args.workload)},
+                   "T": w["T"], "scheme": w["scheme"], "form": "plain",
+                   "timed": "full cycles only (resample, propagate, weigh)"},
+        "roofline": roof,
         "loglik": loglik,
         "moments": [float(v) for v in mom],
     }
     out["latency"] = step_latency(pf, cfg, y, stream, torch, min(K, LATENCY_STEPS))
+    if args.workload == "sv_pl_2p26" and not args.no_batch:
+        wb = WORKLOADS["ll_pl_batch256"]
+        r = measure_batch(args, wb, pf, torch, K, min(W, 5))
+        r.pop("sizes")
+        r.pop("y")
+        out["batched"] = r
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, y)
     print(json.dumps(out), flush=True)
