@@ -299,3 +299,80 @@ def test_errors(pf):
         f.loglik()
     assert e.value.code == pf.EDEGENERATE
     f.close()
+
+
+@pytest.mark.parametrize("model,scheme", [("ll_pl", "stratified"), ("ll_pf", "stratified"),
+                                          ("sv_pl", "systematic"), ("sv_pf", "systematic")])
+def test_fp32_common_state_every_step(pf, orc, model, scheme):
+    """Single precision against the double-precision oracle at every step of
+    a run: before each cycle the oracle is handed the GPU's own particles,
+    then both run that one cycle on the same random words.  Each step's
+    log-likelihood increment is held to 1e-3 and its filtered moments to
+    1e-4 relative (to max(|m|, sd) for the state's mean); ancestors are equal
+    except where a uniform falls within rounding of a CDF value."""
+    n, t_first, T = 1 << 16, 2, 30
+    print(f"fp32 every step {model} n={n} {scheme} T={T}", flush=True)
+    y = C.data(model, T + 1)
+    f = pf.Filter(C.pf_config(pf, model, n, 5, scheme, fp32=True))
+    ocfg = C.oracle_config(orc, model, n, 5, scheme, fp32=True)
+    f.step(y[:t_first])
+    ll_prev = f.loglik()
+    worst_m, worst_ll, flips = 0.0, 0.0, 0
+    for t0 in range(t_first, T):
+        if model == "ll_pl":
+            # the call weighs y_{t0+1} on z_{t0}; moments() then propagates
+            f.step(y[t0:t0 + 1])
+            rec0, _, tt = f.particles()
+        else:
+            rec0, _, tt = f.particles()
+            f.step(y[t0:t0 + 1])
+        ll = f.loglik()
+        ll_inc, ll_prev = ll - ll_prev, ll
+        mom = f.moments()
+        _, anc1, _ = f.particles()
+        assert tt == t0
+        ref = orc.run(ocfg, y[t0:t0 + 1], dump=True,
+                      state0=C.record_to_oracle(model, rec0, t0), t0=t0, y_prev=y[t0 - 1])
+        want = ref["moments"][0, : mom.size]
+        sd = np.sqrt(want[1])
+        errs = [_rel_err(mom[0], want[0], sd), abs(mom[1] - want[1]) / want[1]]
+        errs += [abs(mom[i] - want[i]) / abs(want[i]) for i in range(2, mom.size)]
+        worst_m = max(worst_m, max(errs))
+        worst_ll = max(worst_ll, abs(ll_inc - ref["loglik"][0]))
+        flips = max(flips, int(np.count_nonzero(anc1 != ref["anc"][0])))
+        assert max(errs) <= 1e-4, (t0, mom, want)
+        assert abs(ll_inc - ref["loglik"][0]) <= 1e-3, (t0, ll_inc, ref["loglik"][0])
+        assert flips <= 1e-3 * n, (t0, flips)
+    print(f"worst moment error {worst_m:.2e}, worst increment error {worst_ll:.2e}, "
+          f"most ancestor flips {flips}")
+    f.close()
+
+
+def test_fp32_full_size_trajectory_ll_pl(pf):
+    """The full local-level particle-learning configuration in single
+    precision (N = 2^20, T = 500, stratified) against the oracle's run on the
+    same data and random words (values written by tests/golden/make_fullrun.py
+    from the oracle): |d loglik| <= 1e-3 T over the whole run and at every
+    50th step (scaled to the steps so far).  At this N one run's Monte Carlo
+    s.d. is about 0.004, far inside the bound, so one seed suffices."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ll_pl_2p20_t500.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    n, T = gold["n"], gold["T"]
+    print(f"fp32 full-size trajectory ll_pl n={n} T={T}", flush=True)
+    y = C.data("ll_pl", T, seed=gold["data_seed"])
+    f = pf.Filter(C.pf_config(pf, "ll_pl", n, gold["filter_seed"], "stratified", fp32=True,
+                              keep_ancestors=False))
+    cum_or = np.cumsum(gold["loglik_steps"])
+    done = 0
+    for t in gold["moment_steps"]:
+        f.step(y[done:t + 1])
+        done = t + 1
+        ll = f.loglik()
+        assert abs(ll - cum_or[t]) <= 1e-3 * (t + 1), (t, ll, cum_or[t])
+    d_ll = f.loglik() - cum_or[-1]
+    print(f"loglik {f.loglik():.4f} oracle {cum_or[-1]:.4f} difference {d_ll:.4f}")
+    assert abs(d_ll) <= 1e-3 * T
+    f.close()

@@ -225,3 +225,105 @@ def test_sampled_step_equals_the_full_step(orc, model, scheme):
     if model != "ll_pl":
         anc0, _ = orc.step_slots(cfg, ref["state"][0], 0, 0.0, y[0], slots)
         np.testing.assert_array_equal(anc0, slots)
+
+
+def _z_rms_max(est, ref):
+    """RMS and largest |z| of the seed means of ``est`` (seeds x T) about ``ref``."""
+    est = np.asarray(est)
+    z = (est.mean(0) - ref) / (est.std(0, ddof=1) / np.sqrt(est.shape[0]) + 1e-15)
+    return np.sqrt(np.mean(z**2)), np.abs(z).max()
+
+
+def test_ll_pf_filtered_variance_matches_kalman(orc, y_ll):
+    # moment 1 (weighted Var x_t before resampling) against the Kalman
+    # filter's filtered variance C_t; the predictive variance C_{t-1} + sigma_w2
+    # (an unweighted variance) or E x^2 (no centring) would miss by far
+    _, _, var = cf.kalman_ll(y_ll, 1.0, 0.1, 0.0, 10.0)
+    runs = _runs(orc, orc.LL_PF, 4096, range(16), y_ll, orc.MULTINOMIAL,
+                 sigma_v2=1.0, sigma_w2=0.1, **LL)
+    rms, zmax = _z_rms_max([r["moments"][:, 1] for r in runs], var)
+    assert rms < 1.6 and zmax < 5.0, (rms, zmax)
+
+
+def test_ll_pl_known_parameter_limit_variance_matches_kalman(orc, y_ll):
+    # equal-weight Var x_t after propagation in the known-variance limit
+    _, _, var = cf.kalman_ll(y_ll, 1.0, 0.1, 0.0, 10.0)
+    runs = _runs(orc, orc.LL_PL, 2048, range(12), y_ll, orc.STRATIFIED,
+                 a_v=1e7, b_v=1e7, a_w=1e7, b_w=1e6, **LL)
+    rms, zmax = _z_rms_max([r["moments"][:, 1] for r in runs], var)
+    assert rms < 1.6 and zmax < 5.0, (rms, zmax)
+
+
+def test_sv_pf_filtered_variance_matches_grid_filter(orc, y_sv):
+    _, _, ev = cf.sv_grid_filter(y_sv, MU, PHI, SIG**2, SV0["x0_mean"], SV0["x0_var"],
+                                 grid=1001)
+    runs = _runs(orc, orc.SV_PF, 4096, range(16), y_sv, orc.SYSTEMATIC,
+                 mu=MU, phi=PHI, sigma2=SIG**2, **SV0)
+    rms, zmax = _z_rms_max([r["moments"][:, 1] for r in runs], ev)
+    assert rms < 1.6 and zmax < 5.0, (rms, zmax)
+
+
+def test_ess_special_cases(orc, y_ll):
+    """Effective sample size (sum w)^2 / sum w^2 at the cases that fix it:
+    a flat likelihood gives N; one particle far closer than the rest gives 1;
+    weights that are 1 on n0 particles and underflow to 0 on the others
+    give n0, counted from the particles themselves."""
+    n = 1000
+    flat = orc.run(orc.make_config(orc.LL_PF, n, 3, sigma_v2=1e300, sigma_w2=0.1, **LL),
+                   y_ll[:5])
+    assert np.all(flat["moments"][:, 2] == n)
+    sharp = orc.run(orc.make_config(orc.LL_PF, n, 3, sigma_v2=1e-12, sigma_w2=0.1, **LL),
+                    y_ll[:5])
+    assert np.allclose(sharp["moments"][:, 2], 1.0, rtol=0, atol=1e-9)
+    # half the particles at 0, half at 1e6, no motion; the first resampling
+    # (equal weights at y_prev = 5e5) draws random counts, then y = 0 keeps
+    # weight 1 on the particles at 0 only
+    state0 = np.where(np.arange(n) % 2 == 0, 0.0, 1e6)
+    for seed in range(4):
+        cfg = orc.make_config(orc.LL_PF, n, seed, scheme=orc.MULTINOMIAL, sigma_v2=1.0,
+                              sigma_w2=0.0, **LL)
+        r = orc.run(cfg, np.array([0.0]), dump=True, state0=state0, t0=3, y_prev=5e5)
+        n0 = np.count_nonzero(r["state"][0, 0] == 0.0)
+        assert 0 < n0 < n
+        assert r["moments"][0, 2] == pytest.approx(n0, rel=1e-12)
+    # stochastic volatility: identical particles (no spread, no noise) weigh equally
+    svc = orc.make_config(orc.SV_PF, n, 2, mu=MU, phi=PHI, sigma2=0.0, x0_mean=MU, x0_var=0.0)
+    sv = orc.run(svc, np.array([0.3, -1.2, 0.05]))
+    assert np.allclose(sv["moments"][:, 2], n, rtol=1e-12)
+
+
+def test_sv_pl_ess_and_rao_blackwell_mean(orc, y_sv):
+    """SV-PL moment 5 (ESS) lies in [1, N] and equals N for identical
+    particles.  Moment 6, the Rao-Blackwell mean d/(a-1) of sigma^2 given
+    each particle's path, and moment 4, the mean of the sigma^2 draws that
+    produced the step's states, are both taken under the step's weights: the
+    draw and the path are jointly from the same posterior, so by the tower
+    property both estimate E[sigma^2 | y_1..t] and differ only by the draws'
+    noise (checked over seeds in standard errors; d/a instead of d/(a-1)
+    would be off by 1/(a-1), several percent here)."""
+    n, T = 4096, 20
+    runs = _runs(orc, orc.SV_PL, n, range(12), y_sv[:T], orc.SYSTEMATIC,
+                 prior_mean=[MU * (1 - PHI), PHI], prior_prec=[1.0, 0.0, 1.0],
+                 a_s=2.0, d_s=0.04, **SV0)
+    ess = np.array([r["moments"][:, 5] for r in runs])
+    assert np.all((ess >= 1.0) & (ess <= n))
+    rb = np.array([r["moments"][:, 6] for r in runs])
+    drawn = np.array([r["moments"][:, 4] for r in runs])
+    d = drawn - rb
+    z = d.mean(0) / (d.std(0, ddof=1) / np.sqrt(d.shape[0]))
+    assert np.sqrt(np.mean(z**2)) < 1.8 and np.abs(z).max() < 5.0, z
+    # 1/(a-1) against 1/a: a = a_s + t/2 is at most 12 here
+    assert np.mean(np.abs(d.mean(0)) / rb.mean(0)) < 0.02
+    same = orc.run(orc.make_config(orc.SV_PL, 500, 1, scheme=orc.SYSTEMATIC,
+                                   prior_mean=[MU * (1 - PHI), PHI], prior_prec=[1.0, 0.0, 1.0],
+                                   a_s=1e6, d_s=1e-24, x0_mean=MU, x0_var=0.0), y_sv[:1])
+    # (one step: the batch form of d loses a scale this small to rounding later)
+    assert np.allclose(same["moments"][:, 5], 500, rtol=1e-9)
+
+
+def test_sv_pl_rao_blackwell_mean_in_the_known_parameter_limit(orc, y_sv):
+    runs = _runs(orc, orc.SV_PL, 2048, range(4), y_sv[:40], orc.SYSTEMATIC,
+                 prior_mean=[MU * (1 - PHI), PHI], prior_prec=[1e9, 0.0, 1e9],
+                 a_s=1e7, d_s=1e7 * SIG**2, **SV0)
+    rb = np.array([r["moments"][:, 6] for r in runs])
+    assert np.allclose(rb, SIG**2, rtol=1e-4)
