@@ -242,6 +242,14 @@ int pf_batch_update(pf_batch* b, pf_filter* const* filters, int32_t n);
  * launched), PF_EDEVICE. */
 int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps);
 
+/* Device bytes a batch allocates for itself (beyond its members'
+ * workspaces) with this capacity and ring (ring < 1 means 64) when its
+ * members hold `tiles` tiles in all: the ring of per-step member arguments,
+ * the member table, the global tile map and the batch's progress counters.
+ * A memory budget that admits filters by pf_workspace_bytes charges this
+ * too.  0 for capacity < 1 or tiles < 0.  Host-only (no device call). */
+size_t pf_batch_bytes(int32_t capacity, int32_t ring, int64_t tiles);
+
 /* Release a batch (not its filters).  NULL is accepted. */
 int pf_batch_destroy(pf_batch* b);
 
@@ -291,6 +299,35 @@ int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_ou
  * (its first GPU run faulted; the cause is not yet found).  Use
  * pf_debug_particles for a synchronous copy. */
 int pf_copy_particles_async(pf_filter* f, void* host_dst, size_t bytes, void* copy_stream);
+
+/* ------------------------------------------------------ checkpoints  */
+/* Snapshot and resume of a filter's state, so that a server can pre-empt a
+ * filter (free its device memory) and later continue it.  Everything the
+ * next cycle reads is kept: the current particle record, the latest CDF
+ * (in-tile prefixes, tile tables, totals, cut-point table), the running
+ * log-likelihood, moment partials and error flags, and the host-side step
+ * state (time index, buffer parity, a particle-learning filter's pending
+ * observation).  The random draws are counter-based on (seed, slot, time),
+ * so a restored filter continues exactly as the uninterrupted one would,
+ * bit for bit with the default tile scan (Section 3.2's cycle is a function
+ * of the particles, the CDF and the step's draws).
+ *
+ * pf_checkpoint_bytes: host bytes a snapshot of f takes (0 for NULL); it
+ *   does not change while the filter steps.
+ * pf_checkpoint_save: synchronise f's stream and write the snapshot into
+ *   host_out (caller-owned, bytes >= pf_checkpoint_bytes(f)).  Layout: a
+ *   fixed header (format tag, the configuration, the host-side state)
+ *   followed by the workspace minus the two buffers the next cycle
+ *   overwrites without reading.  Errors: PF_EINVAL, PF_EDEVICE.
+ * pf_checkpoint_restore: load a snapshot into f, which must have been
+ *   created with the same configuration (model, scheme, precision, N, seed,
+ *   flags, parameters, and the same resolved tile size and strategy);
+ *   f's own state is replaced.  f must not be a member of a batch with
+ *   steps queued.  Synchronises f's stream.  Errors: PF_EINVAL (not a
+ *   snapshot, another configuration, truncated), PF_EDEVICE. */
+size_t pf_checkpoint_bytes(const pf_filter* f);
+int pf_checkpoint_save(pf_filter* f, void* host_out, size_t bytes);
+int pf_checkpoint_restore(pf_filter* f, const void* host_in, size_t bytes);
 
 /* Autotuner (a runtime aid, not part of the method): picks the tile size
  * (cfg->items_per_thread), the search strategy (cfg->strategy) and the CDF

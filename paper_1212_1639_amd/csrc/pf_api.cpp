@@ -621,6 +621,161 @@ int pf_timing_read(pf_filter* f, double* total_ms, int64_t* launches) {
     return PF_OK;
 }
 
+// ------------------------------------------------------------ checkpoints
+namespace {
+constexpr uint64_t kCkptMagic = 0x31305450434b4650ull;  // "PFKCPT01"
+constexpr uint32_t kCkptVersion = 1;
+
+// What a snapshot records besides device memory: the configuration the
+// workspace layout follows and the host side of the filter's state.
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version, header_bytes;
+    int32_t model, scheme, precision, strategy, ipt, fields, rsz, num_tiles;
+    int64_t n_particles, pitch;
+    uint64_t seed, flags, ws_total, payload;
+    pf::ModelParams mp;
+    int32_t cur, cdf, have_cdf, pending;
+    double y_pend;
+    uint32_t t, epoch;
+    int32_t weighted_partials, pad;
+};
+
+// The workspace regions a snapshot holds, in address order: everything but
+// the record buffer and the CDF-prefix buffer the next cycle writes without
+// reading (rec[1 - cur], c[1 - cdf]); at most three pieces.
+int live_regions(const pf_filter* f, size_t off[3], size_t len[3]);
+}  // namespace
+
+namespace {
+int live_regions(const pf_filter* f, size_t off[3], size_t len[3]) {
+    const size_t rec_bytes = f->L.rec[1] - f->L.rec[0];
+    const size_t c_bytes = f->L.c[1] - f->L.c[0];
+    size_t dead_off[2] = {f->L.rec[1 - f->cur], f->L.c[1 - f->cdf]};
+    size_t dead_len[2] = {rec_bytes, c_bytes};
+    if (dead_off[1] < dead_off[0]) {
+        std::swap(dead_off[0], dead_off[1]);
+        std::swap(dead_len[0], dead_len[1]);
+    }
+    int k = 0;
+    size_t at = 0;
+    for (int d = 0; d < 2; ++d) {
+        if (dead_off[d] > at) {
+            off[k] = at;
+            len[k++] = dead_off[d] - at;
+        }
+        at = dead_off[d] + dead_len[d];
+    }
+    if (f->L.total > at) {
+        off[k] = at;
+        len[k++] = f->L.total - at;
+    }
+    return k;
+}
+
+size_t ckpt_payload(const pf_filter* f) {
+    return f->L.total - (f->L.rec[1] - f->L.rec[0]) - (f->L.c[1] - f->L.c[0]);
+}
+}  // namespace
+
+size_t pf_checkpoint_bytes(const pf_filter* f) {
+    if (!f) return 0;
+    return sizeof(CkptHeader) + ckpt_payload(f);
+}
+
+int pf_checkpoint_save(pf_filter* f, void* host_out, size_t bytes) {
+    if (!f || !host_out) return fail(PF_EINVAL, "NULL argument");
+    if (bytes < pf_checkpoint_bytes(f)) return fail(PF_EINVAL, "host buffer smaller than pf_checkpoint_bytes()");
+    int rc = f->wait_copies(f->stream);
+    if (rc != PF_OK) return rc;
+    CkptHeader h{};
+    h.magic = kCkptMagic;
+    h.version = kCkptVersion;
+    h.header_bytes = sizeof(CkptHeader);
+    h.model = f->cfg.model;
+    h.scheme = f->cfg.scheme;
+    h.precision = f->cfg.precision;
+    h.strategy = f->L.strategy;
+    h.ipt = f->L.ipt;
+    h.fields = f->L.fields;
+    h.rsz = f->L.rsz;
+    h.num_tiles = f->L.num_tiles;
+    h.n_particles = f->cfg.n_particles;
+    h.pitch = f->L.pitch;
+    h.seed = f->cfg.seed;
+    h.flags = f->cfg.flags;
+    h.ws_total = f->L.total;
+    h.payload = ckpt_payload(f);
+    h.mp = f->mp;
+    h.cur = f->cur;
+    h.cdf = f->cdf;
+    h.have_cdf = f->have_cdf ? 1 : 0;
+    h.pending = f->pending ? 1 : 0;
+    h.y_pend = f->y_pend;
+    h.t = f->t;
+    h.epoch = f->epoch;
+    h.weighted_partials = f->weighted_partials;
+    char* dst = static_cast<char*>(host_out);
+    std::memcpy(dst, &h, sizeof(h));
+    size_t off[3], len[3];
+    const int k = live_regions(f, off, len);
+    size_t pos = sizeof(h);
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < k && e == hipSuccess; ++r) {
+        e = hipMemcpyAsync(dst + pos, f->ws + off[r], len[r], hipMemcpyDeviceToHost, f->stream);
+        pos += len[r];
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_checkpoint_save");
+    return PF_OK;
+}
+
+int pf_checkpoint_restore(pf_filter* f, const void* host_in, size_t bytes) {
+    if (!f || !host_in) return fail(PF_EINVAL, "NULL argument");
+    if (bytes < sizeof(CkptHeader)) return fail(PF_EINVAL, "not a filter snapshot (too short)");
+    CkptHeader h;
+    std::memcpy(&h, host_in, sizeof(h));
+    if (h.magic != kCkptMagic || h.header_bytes != sizeof(CkptHeader))
+        return fail(PF_EINVAL, "not a filter snapshot");
+    if (h.version != kCkptVersion) return fail(PF_EINVAL, "snapshot of another format version");
+    const bool same =
+        h.model == f->cfg.model && h.scheme == f->cfg.scheme && h.precision == f->cfg.precision &&
+        h.strategy == f->L.strategy && h.ipt == f->L.ipt && h.fields == f->L.fields &&
+        h.rsz == f->L.rsz && h.num_tiles == f->L.num_tiles &&
+        h.n_particles == f->cfg.n_particles && h.pitch == f->L.pitch && h.seed == f->cfg.seed &&
+        h.flags == f->cfg.flags && h.ws_total == f->L.total &&
+        std::memcmp(&h.mp, &f->mp, sizeof(h.mp)) == 0;
+    if (!same)
+        return fail(PF_EINVAL, "the snapshot was taken from a filter of another configuration");
+    if (h.payload != ckpt_payload(f) || bytes < sizeof(CkptHeader) + h.payload)
+        return fail(PF_EINVAL, "snapshot truncated");
+    if ((h.cur != 0 && h.cur != 1) || (h.cdf != 0 && h.cdf != 1))
+        return fail(PF_EINVAL, "corrupt snapshot");
+    // nothing queued on the filter may still write its workspace
+    hipError_t e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_checkpoint_restore synchronise");
+    int rc = f->wait_copies(f->stream);
+    if (rc != PF_OK) return rc;
+    f->cur = h.cur;
+    f->cdf = h.cdf;
+    f->have_cdf = h.have_cdf != 0;
+    f->pending = h.pending != 0;
+    f->y_pend = h.y_pend;
+    f->t = h.t;
+    f->epoch = h.epoch;
+    f->weighted_partials = h.weighted_partials;
+    size_t off[3], len[3];
+    const int k = live_regions(f, off, len);
+    const char* src = static_cast<const char*>(host_in) + sizeof(h);
+    for (int r = 0; r < k && e == hipSuccess; ++r) {
+        e = hipMemcpyAsync(f->ws + off[r], src, len[r], hipMemcpyHostToDevice, f->stream);
+        src += len[r];
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+    if (e != hipSuccess) return hip_fail(e, "pf_checkpoint_restore");
+    return PF_OK;
+}
+
 int pf_destroy(pf_filter* f) {
     if (!f) return PF_OK;
     hipError_t e = hipStreamSynchronize(f->stream);
@@ -743,6 +898,23 @@ int check_member(const pf_filter* f, int model, int precision, int ipt) {
 }
 }  // namespace
 
+namespace {
+// Entries of a tile map allocated for `tiles` global tiles (with slack, so
+// that members joining later rarely force a new allocation).
+int64_t map_capacity(int64_t tiles) {
+    return std::max<int64_t>(tiles, 2 * (tiles / 2 + 512));
+}
+}  // namespace
+
+size_t pf_batch_bytes(int32_t capacity, int32_t ring, int64_t tiles) {
+    if (capacity < 1 || tiles < 0) return 0;
+    if (ring < 1) ring = 64;
+    const size_t descs = sizeof(pf::StepArgs) * static_cast<size_t>(ring) * capacity;
+    const size_t base = sizeof(int32_t) * (static_cast<size_t>(capacity) + 1);
+    const size_t map = tiles > 0 ? sizeof(int2) * static_cast<size_t>(map_capacity(tiles)) : 0;
+    return descs + base + map + sizeof(pf::BatchState);
+}
+
 int pf_batch_update(pf_batch* b, pf_filter* const* filters, int32_t n) {
     if (!b) return fail(PF_EINVAL, "batch is NULL");
     if (n < 0 || n > b->capacity || (n > 0 && !filters))
@@ -779,7 +951,7 @@ int pf_batch_update(pf_batch* b, pf_filter* const* filters, int32_t n) {
         if (b->d_map) hipFree(b->d_map);
         b->d_map = nullptr;
         b->map_cap = 0;
-        const int64_t cap = std::max<int64_t>(base[n], 2 * static_cast<int64_t>(base[n] / 2 + 512));
+        const int64_t cap = map_capacity(base[n]);
         e = hipMalloc(reinterpret_cast<void**>(&b->d_map), sizeof(int2) * static_cast<size_t>(cap));
         if (e != hipSuccess) return fail(PF_ENOMEM, "pf_batch_update: hipMalloc of the tile map failed");
         b->map_cap = cap;

@@ -30,7 +30,8 @@ EXPORTS = ["pf_fields", "pf_workspace_bytes", "pf_create", "pf_step", "pf_loglik
            "pf_destroy", "pf_last_error", "pf_batch_create", "pf_batch_update", "pf_batch_step",
            "pf_batch_destroy", "pf_step_batch", "pf_debug_search", "pf_debug_particles",
            "pf_timing_start", "pf_timing_read", "pf_autotune", "pf_autotune_batch",
-           "pf_copy_particles_async"]
+           "pf_copy_particles_async", "pf_checkpoint_bytes", "pf_checkpoint_save",
+           "pf_checkpoint_restore", "pf_batch_bytes"]
 
 
 class PFError(RuntimeError):
@@ -98,13 +99,20 @@ def lib():
         L.pf_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(d)]
         L.pf_timing_start.argtypes = [vp, i64, i64]
         L.pf_copy_particles_async.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.pf_batch_bytes.argtypes = [i32, i32, i64]
+        L.pf_batch_bytes.restype = ctypes.c_size_t
+        L.pf_checkpoint_bytes.argtypes = [vp]
+        L.pf_checkpoint_bytes.restype = ctypes.c_size_t
+        L.pf_checkpoint_save.argtypes = [vp, vp, ctypes.c_size_t]
+        L.pf_checkpoint_restore.argtypes = [vp, vp, ctypes.c_size_t]
         L.pf_autotune.argtypes = [cfgp, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
         L.pf_autotune_batch.argtypes = [cfgp, i32, ctypes.POINTER(d), i64, vp, ctypes.POINTER(d)]
         L.pf_timing_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i64)]
         for name in ("pf_create", "pf_step", "pf_loglik", "pf_moments", "pf_destroy",
                      "pf_batch_create", "pf_batch_update", "pf_batch_step", "pf_batch_destroy",
                      "pf_step_batch",
-                     "pf_debug_search", "pf_debug_particles"):
+                     "pf_debug_search", "pf_debug_particles", "pf_checkpoint_save",
+                     "pf_checkpoint_restore"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -224,6 +232,19 @@ class Filter:
         F = lib().pf_fields(self.cfg.model)
         dt = np.float64 if self.cfg.precision == FP64 else np.float32
         return (F, self.cfg.n_particles), dt
+
+    def checkpoint(self):
+        """Snapshot of the filter's whole state (host bytes, numpy uint8)."""
+        nb = lib().pf_checkpoint_bytes(self._h)
+        buf = np.empty(nb, dtype=np.uint8)
+        _check(lib().pf_checkpoint_save(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+        return buf
+
+    def restore(self, snapshot):
+        """Replace the filter's state by a snapshot of a filter with the same
+        configuration (from checkpoint())."""
+        buf = np.ascontiguousarray(snapshot, dtype=np.uint8)
+        _check(lib().pf_checkpoint_restore(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
 
     def copy_particles_async(self, host, copy_stream):
         """Queue a copy of the current particle record into `host` (a pinned

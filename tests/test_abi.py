@@ -110,3 +110,12 @@ def test_workspace_bytes_and_validation(pf):
     cfg = pf.make_config("sv_pl", 100, 1, prior_prec=[1.0, 2.0, 1.0], a_s=2, d_s=0.04, x0_var=1)
     with pytest.raises(pf.PFError, match="positive definite"):
         pf.workspace_bytes(cfg)
+
+
+def test_checkpoint_calls_without_a_filter(pf):
+    # the snapshot size of no filter is 0; save and restore refuse NULL
+    L = pf.lib()
+    assert L.pf_checkpoint_bytes(None) == 0
+    buf = (ctypes.c_uint8 * 64)()
+    assert L.pf_checkpoint_save(None, buf, 64) == pf.EINVAL
+    assert L.pf_checkpoint_restore(None, buf, 64) == pf.EINVAL

@@ -23,6 +23,8 @@ class FakeBackend:
         self.bpp = bytes_per_particle
         self.members = {}
         self.created = []
+        self.suspended = []
+        self.resumed = []
         self.ticks = 0
 
     def footprint(self, req):
@@ -33,6 +35,24 @@ class FakeBackend:
     def create(self, req):
         f = FakeFilter(req)
         self.created.append(req.id)
+        return f
+
+    def tiles_bound(self, req):
+        return -(-req.n // 256)
+
+    def group_bytes(self, tiles):
+        return self.batch_base + 8 * tiles if tiles or self.batch_base else 0
+
+    batch_base = 0
+
+    def suspend(self, h):
+        self.suspended.append(h.req.id)
+        return list(h.fed)
+
+    def resume(self, req, snap):
+        f = FakeFilter(req)
+        f.fed = list(snap)
+        self.resumed.append(req.id)
         return f
 
     def set_members(self, group, handles):
@@ -131,3 +151,43 @@ def test_capacity_bounds_resident_filters():
     st = srv.run(reqs, realtime=False)
     assert st["completed"] == 10
     assert max(len(v) for v in be.members.values()) <= 4
+
+
+def test_batch_buffers_are_charged_to_the_budget():
+    # every model group's batch holds buffers of its own (here 10,000 bytes
+    # plus 8 per tile): admission leaves room for them, and the bytes in use
+    # count them
+    reqs = _requests(k=80, seed=5)
+    be = FakeBackend()
+    be.batch_base = 10_000
+    budget = 3 * 1024 * 64
+    srv = Server(be, budget_bytes=budget)
+    st = srv.run(reqs, realtime=False)
+    assert st["completed"] == len(reqs)
+    assert st["max_bytes_in_use"] <= budget
+    assert srv.in_use() >= 2 * 10_000   # both groups' buffers stay allocated
+    for r in st["done"]:
+        np.testing.assert_array_equal(r.result["fed"], r.y)
+    # a request that would fit alone but not beside the batch buffers is rejected
+    big = Request(99, 0.0, "ll", budget // 64, np.zeros(3))
+    srv = Server(be, budget_bytes=budget)
+    srv.group_peak = {"ll": 0, "sv": 0}
+    st = srv.run([big], realtime=False)
+    assert st["rejected"] == 1
+
+
+def test_preempted_requests_resume_where_they_stopped():
+    reqs = _requests(k=50, seed=7)
+    be = FakeBackend()
+    srv = Server(be, budget_bytes=10 ** 12)
+    picks = {3: 2, 7: 1, 12: 3}     # tick -> how many residents to pre-empt
+
+    def policy(tick, ids):
+        return ids[:picks.get(tick, 0)]
+
+    st = srv.run(reqs, realtime=False, preempt=policy)
+    assert st["completed"] == len(reqs) and st["preempted"] == 6
+    assert sorted(be.suspended) == sorted(be.resumed) == sorted(srv.preempted)
+    for r in st["done"]:
+        np.testing.assert_array_equal(r.result["fed"], r.y)
+    assert st["particle_steps"] == sum(r.n * r.T for r in reqs)
