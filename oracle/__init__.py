@@ -113,6 +113,9 @@ def lib():
         _lib.or_run_from.argtypes = [ctypes.POINTER(Config), d, ctypes.c_int64, ctypes.c_double,
                                      d, ctypes.c_int64, d, d, i64, d, d]
         _lib.or_run_from.restype = ctypes.c_int
+        _lib.or_run_given.argtypes = [ctypes.POINTER(Config), d, ctypes.c_int64, ctypes.c_double,
+                                      d, ctypes.c_int64, i64, d, d, i64, d, d]
+        _lib.or_run_given.restype = ctypes.c_int
         _lib.or_fields.argtypes = [ctypes.c_int]
         _lib.or_fields.restype = ctypes.c_int
     return _lib
@@ -218,13 +221,15 @@ def make_config(model, n, seed, scheme=MULTINOMIAL, search=SEARCH_BINARY, fp32_w
     return c
 
 
-def run(cfg, y, dump=False, state0=None, t0=0, y_prev=0.0):
+def run(cfg, y, dump=False, state0=None, t0=0, y_prev=0.0, anc_first=None):
     """Run the oracle filter over observations y.
 
     With ``state0`` (fields x N, the model's oracle fields) the run starts
     from those particles as the state after step ``t0`` and ``y`` holds the
     observations of steps t0+1, ...; ``y_prev`` is y_{t0} (the weights of
     the first resampling of the models that weight after propagating).
+    With ``anc_first`` (N 0-based indices) the first step's resampling is
+    replaced by those ancestors; everything else is computed as usual.
     Returns a dict with ``loglik`` (T,), ``moments`` (T, NMOM) and, when
     ``dump`` is set, ``anc`` (T, N), ``state`` (T, F, N) and ``logw`` (T, N).
     """
@@ -242,10 +247,14 @@ def run(cfg, y, dump=False, state0=None, t0=0, y_prev=0.0):
     s0 = None
     if state0 is not None:
         s0 = np.ascontiguousarray(state0, dtype=np.float64).reshape(F, N)
-    rc = lib().or_run_from(ctypes.byref(cfg), _dp(s0) if s0 is not None else None, int(t0),
-                           float(y_prev), _dp(y), T, _dp(ll), _dp(mom),
-                           _ip(anc) if dump else None, _dp(state) if dump else None,
-                           _dp(logw) if dump else None)
+    a0 = None
+    if anc_first is not None:
+        a0 = np.ascontiguousarray(anc_first, dtype=np.int64)
+        assert a0.size == N
+    rc = lib().or_run_given(ctypes.byref(cfg), _dp(s0) if s0 is not None else None, int(t0),
+                            float(y_prev), _dp(y), T, _ip(a0) if a0 is not None else None,
+                            _dp(ll), _dp(mom), _ip(anc) if dump else None,
+                            _dp(state) if dump else None, _dp(logw) if dump else None)
     out = {"rc": rc, "loglik": ll, "moments": mom}
     if dump:
         out.update(anc=anc, state=state, logw=logw)

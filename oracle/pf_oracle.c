@@ -379,7 +379,7 @@ static void sv_pf_slot(const or_config* c, const double* zk, uint32_t j, uint32_
  * Moments (weights w_t, before resampling): E x, Var x, ESS. */
 static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* loglik,
                      double* mom, int64_t* anc_out, double* state_out, double* logw_out,
-                     const double* state0, int64_t t0, double y_prev)
+                     const double* state0, int64_t t0, double y_prev, const int64_t* anc_first)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -410,6 +410,8 @@ static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* log
         const int64_t r = t - t0 - 1; /* output row */
         if (t == 1) {
             for (int64_t j = 0; j < N; ++j) a[j] = j;
+        } else if (r == 0 && anc_first) {
+            memcpy(a, anc_first, sizeof(int64_t) * N);
         } else {
             or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
             or_resample(q, N, u, N, c->search, a);
@@ -444,7 +446,7 @@ static int run_ll_pf(const or_config* c, const double* y, int64_t T, double* log
  * y_t ~ N(0, exp(x_t)).  Same cycle, draws and moments as run_ll_pf. */
 static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* loglik,
                      double* mom, int64_t* anc_out, double* state_out, double* logw_out,
-                     const double* state0, int64_t t0, double y_prev)
+                     const double* state0, int64_t t0, double y_prev, const int64_t* anc_first)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -475,6 +477,8 @@ static int run_sv_pf(const or_config* c, const double* y, int64_t T, double* log
         const int64_t r = t - t0 - 1; /* output row */
         if (t == 1) {
             for (int64_t j = 0; j < N; ++j) a[j] = j;
+        } else if (r == 0 && anc_first) {
+            memcpy(a, anc_first, sizeof(int64_t) * N);
         } else {
             or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
             or_resample(q, N, u, N, c->search, a);
@@ -565,7 +569,7 @@ static void ll_pl_slot(const or_config* c, const double* zk, uint32_t j, uint32_
 
 static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* loglik,
                      double* mom, int64_t* anc_out, double* state_out, double* logw_out,
-                     const double* state0, int64_t t0, double y_prev)
+                     const double* state0, int64_t t0, double y_prev, const int64_t* anc_first)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -604,8 +608,12 @@ static int run_ll_pl(const or_config* c, const double* y, int64_t T, double* log
         or_cdf(lw, N, q, &M, &S);
         if (!(S > 0.0) || !isfinite(S) || !isfinite(M)) { rc = -1; }
         loglik[r] = M + log(S / (double)N);
-        or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
-        or_resample(q, N, u, N, c->search, a);
+        if (r == 0 && anc_first) {
+            memcpy(a, anc_first, sizeof(int64_t) * N);
+        } else {
+            or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
+            or_resample(q, N, u, N, c->search, a);
+        }
         const double av = c->a_v + 0.5 * (double)t, aw = c->a_w + 0.5 * (double)t;
         for (int64_t j = 0; j < N; ++j) {
             double zk[5], out[5];
@@ -762,7 +770,7 @@ static void sv_pl_slot(const or_config* c, const double* zk, uint32_t j, uint32_
  *   mean d/(a-1) of sigma^2 after the update. */
 static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* loglik,
                      double* mom, int64_t* anc_out, double* state_out, double* logw_out,
-                     const double* state0, int64_t t0, double y_prev)
+                     const double* state0, int64_t t0, double y_prev, const int64_t* anc_first)
 {
     const int64_t N = c->n;
     const int fp32 = c->fp32_words;
@@ -797,6 +805,8 @@ static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* log
         const int64_t r = t - t0 - 1; /* output row */
         if (t == 1) {
             for (int64_t j = 0; j < N; ++j) a[j] = j;
+        } else if (r == 0 && anc_first) {
+            memcpy(a, anc_first, sizeof(int64_t) * N);
         } else {
             or_uniforms(c->scheme, c->seed, (uint32_t)t, N, u);
             or_resample(q, N, u, N, c->search, a);
@@ -845,16 +855,37 @@ static int run_sv_pl(const or_config* c, const double* y, int64_t T, double* log
  * y_{t0} whose weights the first resampling uses.  Draws use the absolute
  * time index, so a run from the state after t0 steps continues the same
  * random streams. */
+int or_run_given(const or_config* c, const double* state0, int64_t t0, double y_prev,
+                 const double* y, int64_t T, const int64_t* anc_first, double* loglik,
+                 double* mom, int64_t* anc_out, double* state_out, double* logw_out);
+
 int or_run_from(const or_config* c, const double* state0, int64_t t0, double y_prev,
                 const double* y, int64_t T, double* loglik, double* mom, int64_t* anc_out,
                 double* state_out, double* logw_out)
 {
+    return or_run_given(c, state0, t0, y_prev, y, T, NULL, loglik, mom, anc_out, state_out,
+                        logw_out);
+}
+
+/* As or_run_from, except that the first step's resampling is replaced by
+ * the given ancestors anc_first[0..N) (0-based; NULL: resample as usual).
+ * The rest of that step (propagation, statistics, weights, moments) and
+ * every later step are computed as in or_run_from.  This lets a caller
+ * hold another implementation's propagation and weighting to this one's
+ * arithmetic on exactly the same resampled particles. */
+int or_run_given(const or_config* c, const double* state0, int64_t t0, double y_prev,
+                 const double* y, int64_t T, const int64_t* anc_first, double* loglik,
+                 double* mom, int64_t* anc_out, double* state_out, double* logw_out)
+{
     if (!c || c->n < 1 || T < 0 || t0 < 0 || (t0 > 0 && !state0)) return -2;
+    if (anc_first)
+        for (int64_t j = 0; j < c->n; ++j)
+            if (anc_first[j] < 0 || anc_first[j] >= c->n) return -2;
     switch (c->model) {
-    case OR_LL_PF: return run_ll_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
-    case OR_LL_PL: return run_ll_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
-    case OR_SV_PF: return run_sv_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
-    case OR_SV_PL: return run_sv_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev);
+    case OR_LL_PF: return run_ll_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev, anc_first);
+    case OR_LL_PL: return run_ll_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev, anc_first);
+    case OR_SV_PF: return run_sv_pf(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev, anc_first);
+    case OR_SV_PL: return run_sv_pl(c, y, T, loglik, mom, anc_out, state_out, logw_out, state0, t0, y_prev, anc_first);
     }
     return -2;
 }

@@ -305,11 +305,14 @@ def test_errors(pf):
                                           ("sv_pl", "systematic"), ("sv_pf", "systematic")])
 def test_fp32_common_state_every_step(pf, orc, model, scheme):
     """Single precision against the double-precision oracle at every step of
-    a run: before each cycle the oracle is handed the GPU's own particles,
-    then both run that one cycle on the same random words.  Each step's
-    log-likelihood increment is held to 1e-3 and its filtered moments to
-    1e-4 relative (to max(|m|, sd) for the state's mean); ancestors are equal
-    except where a uniform falls within rounding of a CDF value."""
+    a run.  Before each cycle the oracle is handed the GPU's own particles;
+    it then runs that cycle twice on the same random words: once with its
+    own resampling, to count the slots whose ancestor differs (a uniform
+    within rounding of a CDF value: at most 1e-3 N), and once with the GPU's
+    ancestors, so that the single-precision propagation, weights and
+    moments are held to its arithmetic on exactly the same particles:
+    filtered moments within 1e-4 relative (to max(|m|, sd) for the state's
+    mean) and the step's log-likelihood increment within 1e-3."""
     n, t_first, T = 1 << 16, 2, 30
     print(f"fp32 every step {model} n={n} {scheme} T={T}", flush=True)
     y = C.data(model, T + 1)
@@ -331,17 +334,19 @@ def test_fp32_common_state_every_step(pf, orc, model, scheme):
         mom = f.moments()
         _, anc1, _ = f.particles()
         assert tt == t0
-        ref = orc.run(ocfg, y[t0:t0 + 1], dump=True,
-                      state0=C.record_to_oracle(model, rec0, t0), t0=t0, y_prev=y[t0 - 1])
-        want = ref["moments"][0, : mom.size]
+        state0 = C.record_to_oracle(model, rec0, t0)
+        own = orc.run(ocfg, y[t0:t0 + 1], dump=True, state0=state0, t0=t0, y_prev=y[t0 - 1])
+        same = orc.run(ocfg, y[t0:t0 + 1], state0=state0, t0=t0, y_prev=y[t0 - 1],
+                       anc_first=anc1)
+        want = same["moments"][0, : mom.size]
         sd = np.sqrt(want[1])
         errs = [_rel_err(mom[0], want[0], sd), abs(mom[1] - want[1]) / want[1]]
         errs += [abs(mom[i] - want[i]) / abs(want[i]) for i in range(2, mom.size)]
         worst_m = max(worst_m, max(errs))
-        worst_ll = max(worst_ll, abs(ll_inc - ref["loglik"][0]))
-        flips = max(flips, int(np.count_nonzero(anc1 != ref["anc"][0])))
+        worst_ll = max(worst_ll, abs(ll_inc - same["loglik"][0]))
+        flips = max(flips, int(np.count_nonzero(anc1 != own["anc"][0])))
         assert max(errs) <= 1e-4, (t0, mom, want)
-        assert abs(ll_inc - ref["loglik"][0]) <= 1e-3, (t0, ll_inc, ref["loglik"][0])
+        assert abs(ll_inc - same["loglik"][0]) <= 1e-3, (t0, ll_inc, same["loglik"][0])
         assert flips <= 1e-3 * n, (t0, flips)
     print(f"worst moment error {worst_m:.2e}, worst increment error {worst_ll:.2e}, "
           f"most ancestor flips {flips}")

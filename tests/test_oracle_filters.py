@@ -327,3 +327,39 @@ def test_sv_pl_rao_blackwell_mean_in_the_known_parameter_limit(orc, y_sv):
                  a_s=1e7, d_s=1e7 * SIG**2, **SV0)
     rb = np.array([r["moments"][:, 6] for r in runs])
     assert np.allclose(rb, SIG**2, rtol=1e-4)
+
+
+@pytest.mark.parametrize("model", ["ll_pf", "ll_pl", "sv_pf", "sv_pl"])
+def test_run_given_ancestors(orc, model):
+    """A step run from given ancestors: with the oracle's own ancestors it is
+    the plain step; with other ancestors each slot keeps its own random
+    words, so slot j's move from its ancestor is the same as in the plain
+    step for the bootstrap filters (x_t - x~ depends only on the slot's
+    draws)."""
+    from tests import _cases as C
+    n, t0 = 400, 5
+    y = C.data(model, t0 + 3)
+    cfg = C.oracle_config(orc, model, n, 6, "stratified", fp32=False)
+    full = orc.run(cfg, y, dump=True)
+    st = full["state"][t0 - 1]
+    plain = orc.run(cfg, y[t0:], dump=True, state0=st, t0=t0, y_prev=y[t0 - 1])
+    own = orc.run(cfg, y[t0:], dump=True, state0=st, t0=t0, y_prev=y[t0 - 1],
+                  anc_first=plain["anc"][0])
+    for k in ("anc", "state", "loglik", "moments"):
+        np.testing.assert_array_equal(own[k], plain[k])
+    other = np.random.default_rng(1).integers(0, n, size=n)
+    oth = orc.run(cfg, y[t0:t0 + 1], dump=True, state0=st, t0=t0, y_prev=y[t0 - 1],
+                  anc_first=other)
+    np.testing.assert_array_equal(oth["anc"][0], other)
+    if model in ("ll_pf", "sv_pf"):
+        a = plain["anc"][0]
+        phi = 1.0 if model == "ll_pf" else C.PHI
+        mu = 0.0 if model == "ll_pf" else C.MU
+        step_plain = plain["state"][0, 0] - (mu + phi * (st[0, a] - mu))
+        step_other = oth["state"][0, 0] - (mu + phi * (st[0, other] - mu))
+        np.testing.assert_allclose(step_other, step_plain, rtol=0, atol=1e-12)
+    with pytest.raises(AssertionError):
+        orc.run(cfg, y[t0:], state0=st, t0=t0, y_prev=y[t0 - 1], anc_first=other[:-1])
+    bad = other.copy()
+    bad[3] = n
+    assert orc.run(cfg, y[t0:], state0=st, t0=t0, y_prev=y[t0 - 1], anc_first=bad)["rc"] == -2
