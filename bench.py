@@ -272,6 +272,29 @@ def run_paper(args, w, pf, torch):
                 ph["cycles_and_store"].append(t4 - t3)
         breakdown = {k: _median5(v) * 1e3 for k, v in ph.items()}
         breakdown["store"] = breakdown["cycles_and_store"] - breakdown["cycles"]
+    # the multinomial cycle with the paper's cut-point search (the library's
+    # default: its table in LDS up to 2048 particles, in device memory above)
+    # against bisection per slot, and stratified resampling with the merge
+    # search for reference: device time per cycle, no store
+    search_ms = {}
+    for n in [m for m in (131072, 1048576, 8388608) if m in sizes]:
+        row = {}
+        for name, scheme, strat in (("cutpoint", pf.MULTINOMIAL, pf.SEARCH_CUTPOINT),
+                                    ("bisection", pf.MULTINOMIAL, pf.SEARCH_BINARY),
+                                    ("stratified_merge", pf.STRATIFIED, pf.SEARCH_MERGE)):
+            c = pf.make_config(w["model"], n, 1, scheme=scheme, precision=pf.FP32, strategy=strat,
+                               **w["params"])
+            f = pf.Filter(c, stream=stream)
+            f.step(y[:3])                       # warm-up (the first call only weighs)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            f.step(y[3:])
+            stream.synchronize()
+            row[name] = (time.perf_counter() - t0) * 1e3 / (T - 3)
+            f.close()
+        search_ms[str(n)] = {k: round(v, 4) for k, v in row.items()}
+        print(f"paper_table2 multinomial cycle N={n}: {search_ms[str(n)]}", file=sys.stderr,
+              flush=True)
     nmax = max(table["sp"])
     value = nmax * T / (table["sp"][nmax] * 1e-3)
     out = {
@@ -292,6 +315,7 @@ def run_paper(args, w, pf, torch):
                    "store": "particle record to host memory after every cycle (synchronous)"},
         "table2_ms": {k: {str(n): round(v, 3) for n, v in d.items()} for k, d in table.items()},
         "table3_131072_ms": {k: round(v, 3) for k, v in breakdown.items()},
+        "multinomial_cycle_ms": search_ms,
         "paper_gpu_ms_context": {k: {str(n): v for n, v in d.items()}
                                  for k, d in PAPER_TABLE2_MS.items()},
     }

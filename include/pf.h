@@ -126,6 +126,14 @@ enum pf_strategy {
  * work-group scans them in a fixed order.  Both give the same CDF up to
  * rounding; the default is deterministic and faster on MI355X. */
 #define PF_FLAG_LOOKBACK_SCAN 2
+/* PF_FLAG_TEST_SCAN_STALL: a test aid for the bounded waits of the tile
+ * scans run inside the cycle kernel (the look-back, and the scan of filters
+ * of at most 16 tiles in the kernel's last work-group): every such wait
+ * looks for words no tile writes and gives up after 64 polls, as it would
+ * if a tile never published its sums.  The launches end normally; the next
+ * pf_loglik or pf_moments reports PF_EDEVICE.  The filter's results are
+ * meaningless.  (Without it a wait gives up after 2^22 polls.) */
+#define PF_FLAG_TEST_SCAN_STALL 4
 
 typedef struct pf_config {
     int32_t model;            /* enum pf_model                                 */

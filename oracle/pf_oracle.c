@@ -731,8 +731,17 @@ static void sv_pl_slot(const or_config* c, const double* zk, uint32_t j, uint32_
     words(c->seed, j, t, ST_STEP, 0, w);
     or_box_muller(unif(w[1], fp32), unif(w[2], fp32), g);
     double z_g = g[0], z_x = g[1], u_g = unif(w[3], fp32);
-    words(c->seed, j, t, ST_STEP2, 0, w);
-    or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
+    if (fp32 && c->scheme == OR_SYSTEMATIC) {
+        /* 24-bit uniforms under systematic resampling, whose uniform is
+         * drawn once per step so that word 0 is free: the slot's five
+         * uniforms fit one block, the (z3, z4) pair taking word 0 and the
+         * low bytes of words 1, 2, 3 (as the high 24 bits of a word) */
+        const uint32_t low = ((w[1] & 0xffu) << 8) | ((w[2] & 0xffu) << 16) | ((w[3] & 0xffu) << 24);
+        or_box_muller(unif(w[0], fp32), unif(low, fp32), g);
+    } else {
+        words(c->seed, j, t, ST_STEP2, 0, w);
+        or_box_muller(unif(w[0], fp32), unif(w[1], fp32), g);
+    }
     or_sv_theta(post, z_g, u_g, g[0], g[1], c->seed, j, t, fp32, theta);
     double xt = theta[0] + theta[1] * xp + sqrt(theta[2]) * z_x;
     sums[0] += 1.0;
@@ -764,7 +773,9 @@ static void sv_pl_slot(const or_config* c, const double* zk, uint32_t j, uint32_
  *   step ST_STEP(j,t): word 0 -> resampling uniform; words 1,2 ->
  *   Box-Muller (z1 -> gamma normal, z2 -> x_t), word 3 -> gamma uniform;
  *   ST_STEP2(j,t): words 0,1 -> Box-Muller (z3, z4) for (alpha, beta);
- *   gamma retries g = 0.
+ *   gamma retries g = 0.  With 24-bit uniforms and systematic resampling
+ *   (ST_STEP word 0 unused) the (z3, z4) pair comes from ST_STEP word 0
+ *   and the low bytes of words 1-3 instead (see sv_pl_slot).
  * Moments (weights w_t, before resampling): E x, Var x, E alpha, E beta,
  *   E sigma^2 of the draws that produced x_t, ESS, and the Rao-Blackwell
  *   mean d/(a-1) of sigma^2 after the update. */

@@ -138,7 +138,7 @@ int plan(const pf_config* c, Layout* L) {
         return fail(PF_EINVAL, "unknown search strategy");
     if (c->n_particles < 1 || c->n_particles > INT32_MAX)
         return fail(PF_EINVAL, "n_particles must be in [1, 2^31 - 1]");
-    if (c->flags & ~(PF_FLAG_KEEP_ANCESTORS | PF_FLAG_LOOKBACK_SCAN))
+    if (c->flags & ~(PF_FLAG_KEEP_ANCESTORS | PF_FLAG_LOOKBACK_SCAN | PF_FLAG_TEST_SCAN_STALL))
         return fail(PF_EINVAL, "unknown bits in flags");
     const int ipt = choose_ipt(*c);
     if (ipt != 1 && ipt != 2 && ipt != 4 && ipt != 8)
@@ -312,6 +312,7 @@ struct pf_filter {
         a.scan = L.lookback ? pf::kScanLookback : pf::kScanTiles;
         a.ts = L.ts;
         a.rsz = L.rsz;
+        a.test_stall = (cfg.flags & PF_FLAG_TEST_SCAN_STALL) ? 1 : 0;
         a.ab_out = at<pf::TileAB>(L.ab);
         a.hint_out = at<int32_t>(L.hint);
         a.ab_in = at<pf::TileAB>(L.ab);
@@ -543,7 +544,7 @@ int pf_loglik(pf_filter* f, double* out) {
     if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return hip_fail(e, "pf_loglik copy");
     *out = st.loglik;
-    if (st.flags & pf::kScanStall) return fail(PF_EDEVICE, "a fused tile scan stopped waiting for a tile's sums");
+    if (st.flags & pf::kScanStall) return fail(PF_EDEVICE, "a tile scan in the cycle kernel stopped waiting for a tile's sums");
     if (st.flags & pf::kDegenerate) return fail(PF_EDEGENERATE, "a step's weights were all zero or not finite");
     return PF_OK;
 }
@@ -567,7 +568,7 @@ int pf_moments(pf_filter* f, double* out, int32_t n_out) {
     if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
     if (e != hipSuccess) return hip_fail(e, "pf_moments copy");
     for (int k = 0; k < n_out; ++k) out[k] = k < need ? st.moments[k] : 0.0;
-    if (st.flags & pf::kScanStall) return fail(PF_EDEVICE, "a fused tile scan stopped waiting for a tile's sums");
+    if (st.flags & pf::kScanStall) return fail(PF_EDEVICE, "a tile scan in the cycle kernel stopped waiting for a tile's sums");
     if (st.flags & pf::kDegenerate) return fail(PF_EDEGENERATE, "a step's weights were all zero or not finite");
     return PF_OK;
 }

@@ -110,7 +110,7 @@ struct StepArgs {
     int32_t scan;        // Scan
     int32_t ts;          // particles per tile
     int32_t rsz;         // bytes per record element (4 or 8)
-    int32_t pad0;
+    int32_t test_stall;  // scan waits look for words no tile writes (a test aid)
     uint32_t t;          // time index of this step's draws (1-based)
     uint32_t epoch;      // tag of this launch's look-back words (never 0)
     uint64_t seed;

@@ -35,6 +35,10 @@ namespace pf {
 constexpr int kWave = 64;
 // Largest CDF whose cut-point table is built in LDS by the cycle kernel.
 constexpr int kCutMax = 2048;
+// A tile's sorted uniforms are merged against at most this many LDS windows
+// of the CDF; a wider bracket (a long run of near-zero weights inside it,
+// Section 3.2's worst case) is searched by bisection per uniform instead.
+constexpr int kMaxWindows = 16;
 // Predecessor tiles each lane inspects per look-back round.
 constexpr int kLookPer = 4;
 
@@ -184,9 +188,12 @@ __device__ __forceinline__ Agg wave_agg(Agg v) {
     return v;
 }
 
-// A fused tile scan waits at most this many polls (each followed by a short
-// sleep) for one tile's words before it reports a stall.
+// A tile scan inside the cycle kernel (the fused scan of the last
+// work-group, the look-back) waits at most this many polls (each followed by
+// a short sleep) for one tile's words before it reports a stall.
 constexpr uint32_t kFusedScanSpins = 1u << 22;
+// The same waits under PF_FLAG_TEST_SCAN_STALL.
+constexpr uint32_t kTestSpins = 64;
 
 // ------------------------------------------------------------ look-back words
 // Each 64-bit word = (epoch << 32) | 32 payload bits; relaxed agent-scope
@@ -416,28 +423,22 @@ constexpr bool kSortedKernels = false;
 // Exponential spacing -log U of a resampling word (double precision).
 __device__ __forceinline__ double spacing(uint32_t w0) { return -log(unit64(w0)); }
 
-// Inclusive prefix over a tile in slot order (slot i * BLOCK + tid holds
-// v[i]); v[i] is replaced by its prefix, *total receives the tile's sum.
-// Threads sum IPT consecutive slots (read through LDS with one pad entry per
-// IPT slots), then the threads' sums are scanned.  The same order gives the
-// same bits in every kernel that calls it.  Begins and ends with a barrier.
+// Inclusive prefix over a tile in slot order, slots dealt in blocks (thread
+// tid holds slots tid * IPT + i in v[i]); v[i] is replaced by its prefix,
+// *total receives the tile's sum.  The same order gives the same bits in
+// every kernel that calls it.  Ends with a barrier.
 template <int BLOCK, int IPT>
-__device__ __forceinline__ void tile_incl_prefix(double (&v)[IPT], double* s_buf, double* s_red,
-                                                 double* total) {
+__device__ __forceinline__ void tile_incl_prefix(double (&v)[IPT], double* s_red, double* total) {
     constexpr int NW = BLOCK / kWave;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    auto pad = [](int slot) { return slot + slot / IPT; };
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) s_buf[pad(i * BLOCK + tid)] = v[i];
-    __syncthreads();
-    double run = 0.0, blk[IPT];
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    double run = 0.0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        run += s_buf[tid * (IPT + 1) + i];
-        blk[i] = run;
+        run += v[i];
+        v[i] = run;
     }
     const double incl = wave_incl_sum(run);
+    __syncthreads();
     if (lane == kWave - 1) s_red[wave] = incl;
     __syncthreads();
     double base = 0.0, tot = 0.0;
@@ -445,13 +446,9 @@ __device__ __forceinline__ void tile_incl_prefix(double (&v)[IPT], double* s_buf
         if (q == wave) base = tot;
         tot += s_red[q];
     }
-    double ex = wave_shr1(incl, 0.0);
-    base += ex;
+    base += wave_shr1(incl, 0.0);
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) s_buf[tid * (IPT + 1) + i] = base + blk[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) v[i] = s_buf[pad(i * BLOCK + tid)];
+    for (int i = 0; i < IPT; ++i) v[i] += base;
     *total = tot;
     __syncthreads();
 }
@@ -463,17 +460,16 @@ template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void k_spacing_tiles(uint64_t seed, uint32_t t, int64_t n,
                                                          double* aggE) {
     constexpr int TS = BLOCK * IPT;
-    __shared__ double s_buf[BLOCK * (IPT + 1)];
     __shared__ double s_red[BLOCK / kWave];
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * TS;
     double v[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + threadIdx.x;
+        const int64_t j = j0 + static_cast<int64_t>(threadIdx.x) * IPT + i;
         v[i] = j < n ? spacing(philox(seed, static_cast<uint32_t>(j), t, kStep, 0).w0) : 0.0;
     }
     double tot;
-    tile_incl_prefix<BLOCK, IPT>(v, s_buf, s_red, &tot);
+    tile_incl_prefix<BLOCK, IPT>(v, s_red, &tot);
     if (threadIdx.x == 0) {
         if (j0 + TS >= n)
             tot += spacing(philox(seed, static_cast<uint32_t>(n), t, kStep, 0).w0);
@@ -507,6 +503,39 @@ struct StepSmem {
 };
 
 // ------------------------------------------------------------ the cycle
+// Slots of a tile are dealt to threads in blocks: thread tid holds the IPT
+// consecutive slots j0 + tid * IPT + i, i < IPT.  Sorted uniforms of one
+// thread then have nearby ancestors (found by a short forward walk from the
+// previous one), the records and CDF prefixes a thread writes are contiguous
+// (vector stores), and the tile's prefix needs no transposition.
+
+// Streaming store of v[0 .. IPT) to p[0 .. IPT) (p aligned to IPT elements),
+// in pieces of up to 16 bytes.
+template <typename R, int IPT>
+__device__ __forceinline__ void store_run(G<R>* p, const R (&v)[IPT]) {
+    constexpr int PIECE = (16 / static_cast<int>(sizeof(R))) < IPT ? 16 / static_cast<int>(sizeof(R))
+                                                                    : IPT;
+    typedef R VecT __attribute__((ext_vector_type(PIECE)));
+#pragma unroll
+    for (int i0 = 0; i0 < IPT; i0 += PIECE) {
+        VecT x;
+#pragma unroll
+        for (int k = 0; k < PIECE; ++k) x[k] = v[i0 + k];
+        __builtin_nontemporal_store(x, reinterpret_cast<G<VecT>*>(p + i0));
+    }
+}
+
+// First index in [lo, cnt) of s_q with a value >= u, clamped to cnt - 1,
+// for a caller that knows no index below lo qualifies (the previous, smaller
+// uniform of the same thread ended at lo): a short walk, then bisection.
+// Equal to min(lds_lower_bound(s_q, cnt, u), cnt - 1).
+__device__ __forceinline__ int lds_walk(const double* s_q, int lo, int cnt, double u) {
+    int k = lo;
+    for (int s = 0; s < 8 && k < cnt - 1 && s_q[k] < u; ++s) ++k;
+    if (k < cnt - 1 && s_q[k] < u) k = k + 1 + lds_lower_bound(s_q + k + 1, cnt - 2 - k, u);
+    return k < cnt - 1 ? k : cnt - 1;
+}
+
 // One tile of one filter's cycle (the work of one work-group).
 template <int MODEL, typename R, int BLOCK, int IPT>
 __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
@@ -524,6 +553,8 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     const bool lookback = weight && A.scan == kScanLookback;
     const int64_t n = A.n;
     const int64_t j0 = static_cast<int64_t>(tile) * TS;
+    // first slot of this thread's block
+    const int64_t jt = j0 + static_cast<int64_t>(tid) * IPT;
 
     // ---------------------------------------------------------- 1. ancestors
     // The resampling's first reads (the previous CDF's totals and, for the
@@ -544,7 +575,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     int32_t anc[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
+        const int64_t j = jt + i;
         anc[i] = static_cast<int32_t>(j < n ? j : n - 1);
         if (propagate && j < n) w[i] = philox(A.seed, static_cast<uint32_t>(j), A.t, kStep, 0);
         else w[i] = {0u, 0u, 0u, 0u};
@@ -564,16 +595,15 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
             double u[IPT];
             const int64_t jlast = min(j0 + TS, n) - 1;
             const bool sorted_mult = kSortedKernels && A.scheme == kSortedMultinomial;
+            // the uniforms rise with the slot (a thread's own ones too)
+            const bool sorted_u = A.scheme != kMultinomial;
             if (sorted_mult) {
                 // order statistics from exponential spacings: the tile's
                 // offset and scale come from the spacings' tile scan
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                    u[i] = j < n ? spacing(w[i].w0) : 0.0;
-                }
+                for (int i = 0; i < IPT; ++i) u[i] = jt + i < n ? spacing(w[i].w0) : 0.0;
                 double tot;
-                tile_incl_prefix<BLOCK, IPT>(u, sm.q, sm.red, &tot);
+                tile_incl_prefix<BLOCK, IPT>(u, sm.red, &tot);
                 const TileAB e = gp(A.abE)[tile];
 #pragma unroll
                 for (int i = 0; i < IPT; ++i) u[i] = fma(u[i], e.b, e.a);
@@ -581,31 +611,32 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 if (tid == 0) sm.u_first = u[0];
 #pragma unroll
                 for (int i = 0; i < IPT; ++i)
-                    if (static_cast<int64_t>(i) * BLOCK + tid == last_off) sm.u_last = u[i];
+                    if (static_cast<int64_t>(tid) * IPT + i == last_off) sm.u_last = u[i];
                 __syncthreads();
             } else {
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                    u[i] = resample_uniform<kExact>(A.scheme, j, n, inv_n, w[i].w0, u_sys);
-                }
+                for (int i = 0; i < IPT; ++i)
+                    u[i] = resample_uniform<kExact>(A.scheme, jt + i, n, inv_n, w[i].w0, u_sys);
             }
             const int strategy = A.strategy;
             if (n <= WIN && strategy != kBinary) {
                 // the whole CDF fits one LDS window
                 stage_window<BLOCK>(P, 0, static_cast<int>(n), -INFINITY, sm.q, sm.ta, sm.tb, sm.last);
                 if (strategy == kCutpoint) build_cutpoints<BLOCK>(sm.q, static_cast<int>(n), sm.cut);
+                int kprev = -1;
 #pragma unroll
                 for (int i = 0; i < IPT; ++i) {
                     int k;
                     if (strategy == kCutpoint) {
                         k = cutpoint_draw(sm.q, sm.cut, static_cast<int>(n), u[i]);
+                    } else if (sorted_u && kprev >= 0) {
+                        k = lds_walk(sm.q, kprev, static_cast<int>(n), u[i]);
                     } else {
                         k = lds_lower_bound(sm.q, static_cast<int>(n), u[i]);
                         if (k > n - 1) k = static_cast<int>(n - 1);
                     }
-                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                    if (j < n) anc[i] = k;
+                    kprev = k;
+                    if (jt + i < n) anc[i] = k;
                 }
                 __syncthreads();
             } else if (strategy == kMerge) {
@@ -613,7 +644,6 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 // With the tile-scan table, the hints bound them to the source
                 // tiles of CDF positions j0/N and (j0+TS)/N (one tile of slack
                 // either side for rounding); otherwise search the whole CDF.
-                int64_t lo_b = 0, hi_b = n - 1;
                 const bool indexed = A.scan == kScanTiles;
                 if (wave == 0 || wave == 1) {
                     const int64_t js = wave == 0 ? j0 : jlast;
@@ -655,12 +685,19 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 __syncthreads();
                 // (a_hi < a_lo only if the CDF were decreasing; keep one window)
                 const int64_t a_lo = sm.lo, a_hi = max(sm.hi, sm.lo);
+                if (a_hi - a_lo + 1 > static_cast<int64_t>(kMaxWindows) * WIN) {
+                    // a bracket of more than kMaxWindows windows (a long run of
+                    // near-zero weights between the tile's first and last
+                    // ancestors): bisection per uniform over the whole CDF,
+                    // O(log N) per slot instead of O(run / window)
+#pragma unroll
+                    for (int i = 0; i < IPT; ++i)
+                        if (jt + i < n) anc[i] = static_cast<int32_t>(thread_search(P, u[i], 0, n - 1));
+                } else {
                 uint32_t pending = 0;
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                    if (j < n) pending |= 1u << i;
-                }
+                for (int i = 0; i < IPT; ++i)
+                    if (jt + i < n) pending |= 1u << i;
                 double floor = -INFINITY;
                 for (int64_t w0 = a_lo; w0 <= a_hi; w0 += WIN) {
                     const int cnt = static_cast<int>(min(static_cast<int64_t>(WIN), a_hi - w0 + 1));
@@ -668,7 +705,9 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                     const bool last = (w0 + cnt - 1 == a_hi);
                     const double top = sm.q[cnt - 1];
                     const bool first = (w0 == a_lo);
-
+                    // window index of the previous item's ancestor when it
+                    // was found in this window (the next one lies at or above)
+                    int kprev = -1;
 #pragma unroll
                     for (int i = 0; i < IPT; ++i) {
                         if ((pending >> i) & 1u) {
@@ -677,12 +716,20 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                                 if (first && a_lo > 0 && u[i] <= sm.q[0] && P.at(a_lo - 1) >= u[i]) {
                                     // the bracket was too high (rounding): exact search below
                                     k = thread_search(P, u[i], int64_t(0), a_lo - 1);
+                                    kprev = -1;
                                 } else if (u[i] > top && a_hi < n - 1) {
                                     // above the bracket: exact search beyond it
                                     k = thread_search(P, u[i], a_hi + 1, n - 1);
+                                    kprev = -1;
                                 } else {
-                                    int kk = lds_lower_bound(sm.q, cnt, u[i]);
-                                    if (kk > cnt - 1) kk = cnt - 1;
+                                    int kk;
+                                    if (kprev >= 0) {
+                                        kk = lds_walk(sm.q, kprev, cnt, u[i]);
+                                    } else {
+                                        kk = lds_lower_bound(sm.q, cnt, u[i]);
+                                        if (kk > cnt - 1) kk = cnt - 1;
+                                    }
+                                    kprev = kk;
                                     k = w0 + kk;
                                 }
                                 anc[i] = static_cast<int32_t>(k);
@@ -693,21 +740,18 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                     floor = top;
                     __syncthreads();
                 }
+                }
             } else if (strategy == kCutpoint && A.cut_in) {
                 // the paper's cut-point method with the table in device memory
                 G<const int32_t>* table = gp(A.cut_in);
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                    if (j < n) anc[i] = static_cast<int32_t>(cut_draw_global(P, table, u[i]));
-                }
+                for (int i = 0; i < IPT; ++i)
+                    if (jt + i < n) anc[i] = static_cast<int32_t>(cut_draw_global(P, table, u[i]));
             } else {
                 // bisection per slot over the tiled CDF
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-                    if (j < n) anc[i] = static_cast<int32_t>(thread_search(P, u[i], 0, n - 1));
-                }
+                for (int i = 0; i < IPT; ++i)
+                    if (jt + i < n) anc[i] = static_cast<int32_t>(thread_search(P, u[i], 0, n - 1));
             }
         }
     }
@@ -717,52 +761,71 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     G<const R>* rin = gp(static_cast<const R*>(A.rec_in));
     G<R>* rout = gp(static_cast<R*>(A.rec_out));
     G<int32_t>* anc_out = A.anc_out ? gp(A.anc_out) : nullptr;
-    R lw[IPT];
-    // moment partials in the weights' precision: weighted ones relative to
-    // the thread's running max (rescaled when it grows), equal-weight ones
-    // as plain sums; folded into double precision across the tile below
+    const bool full = jt + IPT <= n;   // all of the thread's slots are particles
+    // single precision under systematic resampling: a slot's draws fit one
+    // Philox block (the model decides whether it needs more)
+    const bool one_block = sizeof(R) == 4 && A.scheme == kSystematicScheme;
     using M = Math<R>;
-    R pm = R(-INFINITY), pe = R(0), pe2 = R(0);
+    // ew[i] = exp(l_i - pm): the item's weight relative to the thread's
+    // reference pm (its first weight, raised when a later one exceeds it by
+    // more than kRefSlack, which keeps every ew below e^kRefSlack); tmx is
+    // the thread's largest log-weight.  The tile CDF reuses ew, so each
+    // particle takes one exponential.  Moment partials: weighted ones
+    // relative to pm, equal-weight ones as plain sums; folded into double
+    // precision across the tile below.
+    constexpr float kRefSlack = 32.0f;
+    R ew[IPT];
+    R pm = R(-INFINITY), tmx = R(-INFINITY), pe = R(0), pe2 = R(0);
     R pg[NG];
 #pragma unroll
     for (int k = 0; k < NG; ++k) pg[k] = R(0);
+    R zout[F][IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         // slot and ancestor indices fit 32 bits (N < 2^31): uniform per-field
         // base pointers plus a 32-bit offset keep the address math scalar
-        const uint32_t j = static_cast<uint32_t>(j0) + static_cast<uint32_t>(i * BLOCK + tid);
-        lw[i] = R(-INFINITY);
+        const uint32_t j = static_cast<uint32_t>(jt) + static_cast<uint32_t>(i);
+        ew[i] = R(0);
+#pragma unroll
+        for (int f = 0; f < F; ++f) zout[f][i] = R(0);
         if (static_cast<int64_t>(j) < n) {
             const uint32_t a = static_cast<uint32_t>(anc[i]);
             R z[F], zn[F];
 #pragma unroll
-            // records are read once and written once per cycle: streaming
-            // (non-temporal) accesses keep them from displacing the CDF
-            // window and tables in the caches
-            for (int f = 0; f < F; ++f) z[f] = __builtin_nontemporal_load(&(rin + f * A.pitch)[a]);
+            // ordinary (cached) loads: a thread's slots are consecutive, so
+            // the IPT gathers of one field share cache lines (streaming loads
+            // would fetch each line once per load)
+            for (int f = 0; f < F; ++f) z[f] = (rin + f * A.pitch)[a];
             R g[NG];
             if (propagate) {
-                MD::template propagate<R>(p, A.seed, j, A.t, A.y_prop, w[i], z, zn, g);
+                MD::template propagate<R>(p, A.seed, j, A.t, A.y_prop, w[i], z, zn, g, one_block);
 #pragma unroll
-                for (int f = 0; f < F; ++f) __builtin_nontemporal_store(zn[f], &(rout + f * A.pitch)[j]);
+                for (int f = 0; f < F; ++f) zout[f][i] = zn[f];
             } else {
 #pragma unroll
                 for (int f = 0; f < F; ++f) zn[f] = z[f];
                 MD::template terms<R>(p, A.t, zn, g);
             }
-            if (weight) lw[i] = MD::template logw<R>(p, zn, A.y_weight);
             if (anc_out) anc_out[j] = anc[i];
-            if (weighted_mom) {
-                const R l = lw[i];
-                if (l > pm) {
+            const R l = weight ? MD::template logw<R>(p, zn, A.y_weight) : R(-INFINITY);
+            if (weight) {
+                tmx = fmax(tmx, l);
+                if (i == 0) pm = l;
+                if (l > pm + R(kRefSlack) || (pm == R(-INFINITY) && l > pm)) {
+                    // (rare) a new reference: rescale what is relative to the old one
                     const R sc = M::exp(pm - l);
+#pragma unroll
+                    for (int k = 0; k < i; ++k) ew[k] *= sc;
                     pe *= sc;
                     pe2 *= sc * sc;
 #pragma unroll
                     for (int k = 0; k < NG; ++k) pg[k] *= sc;
                     pm = l;
                 }
-                const R e = (l == R(-INFINITY)) ? R(0) : M::exp(l - pm);
+                ew[i] = (l == R(-INFINITY)) ? R(0) : M::exp(l - pm);
+            }
+            if (weighted_mom) {
+                const R e = ew[i];
                 pe += e;
                 pe2 += e * e;
 #pragma unroll
@@ -774,14 +837,28 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
             }
         }
     }
+    if (propagate) {
+        // the new record: each field's IPT values of this thread are contiguous
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            G<R>* dst = rout + f * A.pitch + jt;
+            if (full) {
+                store_run<R, IPT>(dst, zout[f]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if (jt + i < n) __builtin_nontemporal_store(zout[f][i], dst + i);
+            }
+        }
+    }
 
     // ---------------------------------------------------------- moment partials
     {
         // The threads' partials (weighted ones relative to the thread's
-        // running max) are brought to the tile's max and summed in a fixed
-        // order: with room in the LDS window, every sum is folded by 32
-        // lanes over eight threads' entries each and then across the lanes;
-        // otherwise by wave reductions and a fold over the waves.
+        // reference) are brought to the tile's largest reference and summed
+        // in a fixed order: with room in the LDS window, every sum is folded
+        // by 32 lanes over eight threads' entries each and then across the
+        // lanes; otherwise by wave reductions and a fold over the waves.
         constexpr int NS = 2 + NG;  // e, e^2, e g[0 .. NG)
         constexpr bool kLdsFold = BLOCK == 256 && NS <= BLOCK / 32 && NS * BLOCK <= WIN;
         const double tm = static_cast<double>(pm);
@@ -855,34 +932,25 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     if (!weight) return;
 
     // ---------------------------------------------------------- 3. tile CDF
-    R rloc = R(-INFINITY);
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) rloc = fmax(rloc, lw[i]);
-    const double mloc = wave_max_r(rloc);
+    const double mloc = wave_max_r(tmx);
     if (lane == 0) sm.red[wave] = mloc;
     __syncthreads();
     double mb = -INFINITY;
     for (int q = 0; q < NW; ++q) mb = fmax(mb, sm.red[q]);
-    // e_k = exp(l_k - m_b) in the weights' precision, staged in slot order.
-    // The blocked scan below has each thread read IPT consecutive slots; one
-    // pad entry per IPT slots keeps those reads off a common LDS bank.
-    auto pad = [](int slot) { return slot + slot / IPT; };
-    const R mbr = static_cast<R>(mb);
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const R l = lw[i];
-        const double e = (l == R(-INFINITY) || mb == -INFINITY)
-                             ? 0.0
-                             : static_cast<double>(Math<R>::exp(l - mbr));
-        sm.q[pad(i * BLOCK + tid)] = e;
+    // e_k = exp(l_k - m_b) = ew_k exp(pm - m_b): one exponential per thread,
+    // in double precision where the weights' precision would underflow
+    double fac = 0.0;
+    if (mb != -INFINITY && pm != R(-INFINITY)) {
+        const double d = static_cast<double>(pm) - mb;
+        fac = (sizeof(R) == 4 && d > -80.0) ? static_cast<double>(M::exp(static_cast<R>(d)))
+                                             : exp(d);
     }
-    __syncthreads();
-    // blocked scan: thread owns IPT consecutive slots
+    // the thread's own IPT slots, then the threads' sums scanned
     double v[IPT];
     double run = 0.0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        run += sm.q[tid * (IPT + 1) + i];
+        run += static_cast<double>(ew[i]) * fac;
         v[i] = run;
     }
     const double tincl = wave_incl_sum(run);
@@ -906,30 +974,39 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     for (int q = 0; q < wave; ++q) carry = fmax(carry, sm.red[2 * NW + q]);
     double wex = wave_shr1(wmax, -INFINITY);
     carry = fmax(carry, wex);
-    // back to slot order through LDS, so that the stores are coalesced;
     // single precision rounds toward zero so that a tile's last prefix never
     // exceeds the tile total the scan uses
+    R cst[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const double cval = fmax(base + v[i], carry);
-        sm.q[tid * (IPT + 1) + i] =
-            sizeof(R) == 4 ? static_cast<double>(__double2float_rz(cval)) : cval;
-    }
-    __syncthreads();
-    if (!lookback && tid < kSegments) {
-        // segment samples of this tile's prefix (the last valid element for
-        // segments that run past N)
-        constexpr int SEG = TS / kSegments;
-        int64_t pos = static_cast<int64_t>(tid + 1) * SEG - 1;
-        if (j0 + pos > n - 1) pos = n - 1 - j0;
-        gp(static_cast<R*>(A.samp_out))[static_cast<int64_t>(tile) * kSegments + tid] =
-            static_cast<R>(sm.q[pad(static_cast<int>(pos))]);
+        cst[i] = sizeof(R) == 4 ? static_cast<R>(__double2float_rz(cval)) : static_cast<R>(cval);
     }
     G<R>* cout = gp(static_cast<R*>(A.c_out));
+    if (full) {
+        store_run<R, IPT>(cout + jt, cst);
+    } else {
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const int64_t j = j0 + static_cast<int64_t>(i) * BLOCK + tid;
-        if (j < n) __builtin_nontemporal_store(static_cast<R>(sm.q[pad(i * BLOCK + tid)]), &cout[j]);
+        for (int i = 0; i < IPT; ++i)
+            if (jt + i < n) __builtin_nontemporal_store(cst[i], cout + jt + i);
+    }
+    if (!lookback) {
+        // segment samples of this tile's prefix: segment s ends at offset
+        // (s + 1) SEG - 1, the last slot of a thread; segments that run past
+        // N take the last particle's value, written by the thread holding it
+        constexpr int SEG = TS / kSegments;
+        static_assert(SEG % IPT == 0, "a segment ends on a thread's last slot");
+        G<R>* samp = gp(static_cast<R*>(A.samp_out)) + static_cast<int64_t>(tile) * kSegments;
+        const int64_t plast = min(static_cast<int64_t>(TS), n - j0) - 1;
+        const int off_end = tid * IPT + IPT - 1;
+        if ((off_end + 1) % SEG == 0 && off_end <= plast) samp[off_end / SEG] = cst[IPT - 1];
+        if (plast < TS - 1 && tid == static_cast<int>(plast / IPT)) {
+            R vl = cst[0];
+#pragma unroll
+            for (int i = 1; i < IPT; ++i)
+                if (i == static_cast<int>(plast % IPT)) vl = cst[i];
+            for (int s = static_cast<int>((plast + 1) / SEG); s < kSegments; ++s) samp[s] = vl;
+        }
     }
     const Agg mine{mb, mb == -INFINITY ? 0.0 : total};
 
@@ -960,7 +1037,9 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
         __syncthreads();
         if (!scan_here) return;
         if (tid == 0) __hip_atomic_store(&A.st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t epoch = A.epoch;
+        // (a test run waits for words no tile writes, and gives up sooner)
+        const uint32_t epoch = A.test_stall ? (A.epoch ^ 0x80000000u) : A.epoch;
+        const uint32_t spin_limit = A.test_stall ? kTestSpins : kFusedScanSpins;
         const uint64_t* status = A.status;
         DevState* st = A.st;
         // all of the thread's words are requested at once; a tile whose words
@@ -989,7 +1068,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 } else {
                     const uint64_t* p = status + static_cast<int64_t>(b0 + k) * kStatusWords;
                     for (uint32_t spin = 0; !get_agg(p, epoch, v); ++spin) {
-                        if (spin >= kFusedScanSpins) {
+                        if (spin >= spin_limit) {
                             atomicOr(&st->flags, kScanStall);
                             v = agg_identity();
                             break;
@@ -1010,6 +1089,9 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
     // ---------------------------------------------------------- 4. look-back
     if (wave == 0) {
         const uint32_t epoch = A.epoch;
+        // (a test run waits for words no tile writes, and gives up sooner)
+        const uint32_t wait_epoch = A.test_stall ? (epoch ^ 0x80000000u) : epoch;
+        const uint32_t spin_limit = A.test_stall ? kTestSpins : kFusedScanSpins;
         uint64_t* st = A.status;
         if (lane == 0) put_agg(st + static_cast<int64_t>(tile) * kStatusWords, epoch, mine);
         // each lane covers kLookPer consecutive predecessors (nearest first),
@@ -1029,9 +1111,17 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                     bool incl = true;  // before tile 0: the inclusive identity
                     if (idx >= 0) {
                         const uint64_t* s = st + idx * kStatusWords;
-                        while (true) {
-                            if (get_agg(s + 4, epoch, val)) { incl = true; break; }
-                            if (get_agg(s, epoch, val)) { incl = false; break; }
+                        for (uint32_t spin = 0;; ++spin) {
+                            if (get_agg(s + 4, wait_epoch, val)) { incl = true; break; }
+                            if (get_agg(s, wait_epoch, val)) { incl = false; break; }
+                            if (spin >= spin_limit) {
+                                // the predecessor never published: report it
+                                // and end the look-back here
+                                atomicOr(&A.st->flags, kScanStall);
+                                val = agg_identity();
+                                incl = true;
+                                break;
+                            }
                             __builtin_amdgcn_s_sleep(1);
                         }
                     }
@@ -1856,8 +1946,9 @@ __global__ void k_cutpoint_draw(PlainCdf cdf, const int32_t* table, const double
     const int64_t n = cdf.n;
     const double uj = u[j];
     const double ce = ceil(static_cast<double>(n) * uj);
-    const int64_t e = ce < 1.0 ? 1 : (ce > static_cast<double>(n) ? n : static_cast<int64_t>(ce));
-    int64_t k = table[e - 1];
+    const int64_t e = !(ce >= 1.0) ? 1 : (ce > static_cast<double>(n) ? n : static_cast<int64_t>(ce));
+    // (a table built from a CDF that failed the check may hold anything)
+    int64_t k = min(max(static_cast<int64_t>(table[e - 1]), int64_t(0)), n - 1);
     for (int c = 0; c < 16 && k < n - 1 && uj > cdf.q[k]; ++c) ++k;
     if (k < n - 1 && uj > cdf.q[k]) k = thread_search(cdf, uj, k + 1, n - 1);
     anc[j] = static_cast<int32_t>(k);
@@ -1909,6 +2000,15 @@ __global__ __launch_bounds__(BLOCK) void k_search_merge(PlainCdf cdf, const doub
     uint32_t pending = 0;
     for (int i = 0; i < IPT; ++i)
         if (j0 + static_cast<int64_t>(i) * BLOCK + tid < m) pending |= 1u << i;
+    if (a_hi - a_lo + 1 > static_cast<int64_t>(kMaxWindows) * WIN) {
+        // a bracket of more than kMaxWindows windows: bisection per uniform
+        // inside it (exact: every answer lies in [a_lo, a_hi])
+        for (int i = 0; i < IPT; ++i)
+            if ((pending >> i) & 1u)
+                anc[j0 + static_cast<int64_t>(i) * BLOCK + tid] =
+                    static_cast<int32_t>(thread_search(cdf, uu[i], a_lo, a_hi));
+        return;
+    }
     for (int64_t w0 = a_lo; w0 <= a_hi; w0 += WIN) {
         const int cnt = static_cast<int>(min(static_cast<int64_t>(WIN), a_hi - w0 + 1));
         for (int k = tid; k < cnt; k += BLOCK) s_q[k] = cdf.q[w0 + k];

@@ -160,7 +160,7 @@ struct ModelDef<kLLPF> {
     // Step 1: x_t = x~_{t-1} + sqrt(sigma_w2) Z; Z from words 1, 2 of kStep.
     template <typename R>
     __device__ static void propagate(const ModelParams& p, uint64_t, uint32_t, uint32_t, double,
-                                     const Words& w, const R* z, R* zn, R* g) {
+                                     const Words& w, const R* z, R* zn, R* g, bool) {
         R a, b;
         box_muller(unit<R>(w.w1), unit<R>(w.w2), a, b);
         zn[0] = z[0] + Math<R>::sqrt(R(p.sigma_w2)) * a;
@@ -190,7 +190,7 @@ struct ModelDef<kSVPF> {
     }
     template <typename R>
     __device__ static void propagate(const ModelParams& p, uint64_t, uint32_t, uint32_t, double,
-                                     const Words& w, const R* z, R* zn, R* g) {
+                                     const Words& w, const R* z, R* zn, R* g, bool) {
         R a, b;
         box_muller(unit<R>(w.w1), unit<R>(w.w2), a, b);
         zn[0] = R(p.mu) + R(p.phi) * (z[0] - R(p.mu)) + Math<R>::sqrt(R(p.sigma2)) * a;
@@ -242,7 +242,7 @@ struct ModelDef<kLLPL> {
     // uniform; kStep2 0,1 -> Box-Muller (gamma_w normal), 2 -> gamma_w uniform.
     template <typename R>
     __device__ static void propagate(const ModelParams& p, uint64_t seed, uint32_t j, uint32_t t,
-                                     double y, const Words& w, const R* z, R* zn, R* g) {
+                                     double y, const Words& w, const R* z, R* zn, R* g, bool) {
         R zx, zv;
         box_muller(unit<R>(w.w1), unit<R>(w.w2), zx, zv);
         const R uv = unit<R>(w.w3);
@@ -311,16 +311,25 @@ struct ModelDef<kSVPL> {
     // (alpha, beta) = m + sigma L^{-T} (z3, z4), Lambda = L L'; x_t = alpha +
     // beta x~ + sigma z_x; statistics updated with the pair (x~, x_t).
     // Words: kStep 1,2 -> Box-Muller (gamma normal, z_x), 3 -> gamma uniform;
-    // kStep2 0,1 -> Box-Muller (z3, z4).
+    // kStep2 0,1 -> Box-Muller (z3, z4).  With one_block (single precision
+    // under systematic resampling, whose uniform is drawn once per step, so
+    // kStep word 0 is free) the five 24-bit uniforms fit one block: the
+    // pair for (z3, z4) is word 0 and the low bytes of words 1, 2, 3.
     template <typename R>
     __device__ static void propagate(const ModelParams& p, uint64_t seed, uint32_t j, uint32_t t,
-                                     double, const Words& w, const R* z, R* zn, R* g) {
+                                     double, const Words& w, const R* z, R* zn, R* g,
+                                     bool one_block) {
         R zg, zx;
         box_muller(unit<R>(w.w1), unit<R>(w.w2), zg, zx);
         const R ug = unit<R>(w.w3);
-        const Words w2 = philox(seed, j, t, kStep2, 0);
         R z3, z4;
-        box_muller(unit<R>(w2.w0), unit<R>(w2.w1), z3, z4);
+        if (one_block) {
+            const uint32_t low = ((w.w1 & 0xffu) << 8) | ((w.w2 & 0xffu) << 16) | ((w.w3 & 0xffu) << 24);
+            box_muller(unit<R>(w.w0), unit<R>(low), z3, z4);
+        } else {
+            const Words w2 = philox(seed, j, t, kStep2, 0);
+            box_muller(unit<R>(w2.w0), unit<R>(w2.w1), z3, z4);
+        }
         using M = Math<R>;
         const R nprev = R(t) - R(1);
         const R L00 = R(p.p0) + nprev, L01 = z[1], L11 = z[2];

@@ -22,6 +22,7 @@ SEARCH_AUTO, SEARCH_BINARY, SEARCH_CUTPOINT, SEARCH_MERGE = 0, 1, 2, 3
 OK, EINVAL, ENOMEM, EDEVICE, EDEGENERATE = 0, -1, -2, -3, -4
 FLAG_KEEP_ANCESTORS = 1
 FLAG_LOOKBACK_SCAN = 2
+FLAG_TEST_SCAN_STALL = 4
 N_MOMENTS = {LL_PF: 3, LL_PL: 6, SV_PF: 3, SV_PL: 7}
 MODEL_NAMES = {"ll_pf": LL_PF, "ll_pl": LL_PL, "sv_pf": SV_PF, "sv_pl": SV_PL}
 

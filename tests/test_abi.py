@@ -58,7 +58,7 @@ def test_workspace_bytes_and_validation(pf):
     bad = [
         dict(n=0), dict(n=1 << 31), dict(scheme=7), dict(scheme=4), dict(precision=3),
         dict(strategy=9),
-        dict(items_per_thread=3), dict(x0_var=-1.0), dict(a_v=0.5), dict(flags=4),
+        dict(items_per_thread=3), dict(x0_var=-1.0), dict(a_v=0.5), dict(flags=8),
     ]
     for b in bad:
         kw = dict(model="ll_pl", n=1024, seed=1, scheme=pf.STRATIFIED, a_v=2, b_v=1, a_w=2, b_w=1,

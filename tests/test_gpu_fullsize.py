@@ -52,20 +52,23 @@ def test_ll_pl_2p20_fp32_one_cycle(pf, orc):
     f.close()
     assert tt == t0 and tt1 == t0 + 1
     ocfg = C.oracle_config(orc, model, n, 3, scheme, fp32=True)
-    ref = orc.run(ocfg, y[t0:t0 + 1], dump=True, state0=C.record_to_oracle(model, rec0, t0),
-                  t0=t0, y_prev=y[t0 - 1])
-    want = ref["moments"][0, : mom.size]
+    state0 = C.record_to_oracle(model, rec0, t0)
+    ref = orc.run(ocfg, y[t0:t0 + 1], dump=True, state0=state0, t0=t0, y_prev=y[t0 - 1])
+    # moments and records on the GPU's own ancestors (a flipped slot takes an
+    # unrelated neighbouring particle, which is no arithmetic error)
+    given = orc.run(ocfg, y[t0:t0 + 1], dump=True, state0=state0, t0=t0, y_prev=y[t0 - 1],
+                    anc_first=anc1)
+    want = given["moments"][0, : mom.size]
     sd = np.sqrt(want[1])
     assert _rel_err(mom[0], want[0], sd) <= 1e-4, (mom, want)
     assert abs(mom[1] - want[1]) <= 1e-4 * want[1]
     for i in range(2, mom.size):
         assert abs(mom[i] - want[i]) <= 1e-4 * abs(want[i]), (i, mom[i], want[i])
-    assert abs(ll_inc - ref["loglik"][0]) <= 1e-3
+    assert abs(ll_inc - given["loglik"][0]) <= 1e-3
     flips = np.count_nonzero(anc1 != ref["anc"][0])
     print("ancestor flips", flips, "of", n, flush=True)
     assert flips <= 1e-3 * n
-    same = anc1 == ref["anc"][0]
-    close = np.isclose(rec1[:, same], ref["state"][0][:, same], rtol=1e-4, atol=1e-5)
+    close = np.isclose(rec1, given["state"][0], rtol=1e-4, atol=1e-5)
     assert np.count_nonzero(~close) <= 1e-4 * n * rec1.shape[0]
 
 
@@ -169,3 +172,55 @@ def test_batch256_equals_alone(pf):
     b.close()
     for f in alone + together:
         f.close()
+
+
+def test_near_degenerate_weights_at_scale(pf, orc):
+    """The fused cycle when a handful of particles carry the weight (Section
+    3.2's hard case for the search), at N = 2^22 in double precision: a
+    sharp likelihood (sigma_v2 = 1e-3) and two outlying observations leave a
+    few surviving families, whose contiguous offspring then form long runs of
+    near-zero weight between heavy ones.  Every step's sampled slots (tile
+    and window edges included) match the oracle's recomputation from the
+    GPU's own particles, the log-likelihood increment equals the
+    log-mean-exp of the new particles' weights, and no step takes longer
+    than 50 ms (a tile whose bracket spans more than 16 LDS windows bisects
+    per slot instead of walking the windows)."""
+    import time
+    n, T = 1 << 22, 7
+    params = dict(C.LL_PARAMS, sigma_v2=1e-3)
+    y = C.data("ll_pf", T).copy()
+    y[2] += 3.0
+    y[4] -= 2.5
+    print(f"near-degenerate weights ll_pf n={n} T={T}", flush=True)
+    cfg = pf.make_config("ll_pf", n, 17, scheme=pf.SYSTEMATIC, precision=pf.FP64,
+                         flags=pf.FLAG_KEEP_ANCESTORS, **params)
+    ocfg = orc.make_config(orc.LL_PF, n, 17, scheme=orc.SYSTEMATIC, **params)
+    rng = np.random.default_rng(5)
+    edges = np.array([0, 1, 1023, 1024, 2047, 2048, 4095, 4096, n // 2, n - 1025, n - 1024,
+                      n - 2, n - 1])
+    slots = np.unique(np.concatenate([edges, rng.integers(0, n, size=3000)]))
+    f = pf.Filter(cfg)
+    f.step(y[:1])
+    ll_prev = f.loglik()
+    worst = 0.0
+    for t in range(1, T):
+        rec0, _, tt = f.particles()
+        assert tt == t
+        t_start = time.perf_counter()
+        f.step(y[t:t + 1])
+        ll = f.loglik()
+        worst = max(worst, time.perf_counter() - t_start)
+        rec1, anc1, _ = f.particles()
+        a_or, st_or = orc.step_slots(ocfg, rec0, t, y[t - 1], y[t], slots)
+        np.testing.assert_array_equal(anc1[slots], a_or)
+        np.testing.assert_allclose(rec1[0, slots], st_or[0], rtol=1e-12, atol=1e-12)
+        lw = -0.5 * np.log(2 * np.pi * params["sigma_v2"]) - 0.5 * (y[t] - rec1[0]) ** 2 / params["sigma_v2"]
+        m = lw.max()
+        want_inc = m + np.log(np.mean(np.exp(lw - m)))
+        assert abs((ll - ll_prev) - want_inc) < 1e-9 * max(1.0, abs(want_inc)), (t, ll - ll_prev, want_inc)
+        ll_prev = ll
+        ess = np.exp(lw - m).sum() ** 2 / np.exp(2 * (lw - m)).sum()
+        print(f"step {t + 1}: {np.unique(anc1).size} distinct ancestors, ESS {ess:.1f}", flush=True)
+    print(f"slowest step {1e3 * worst:.2f} ms", flush=True)
+    assert worst < 0.05
+    f.close()

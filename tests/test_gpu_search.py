@@ -99,3 +99,29 @@ def test_empty_uniforms(dev):
     q = torch.tensor([0.5, 1.0], dtype=torch.float64, device=dev)
     u = torch.empty(0, dtype=torch.float64, device=dev)
     assert pf.debug_search(q, u, pf.SEARCH_MERGE).numel() == 0
+
+
+def test_merge_over_a_long_flat_run(dev):
+    """Section 3.2's worst case for a merge of sorted uniforms: two heavy
+    entries at the ends of a CDF that is flat for 2^22 - 2 entries between
+    them, so the tile of uniforms that straddles the jump brackets the
+    whole CDF.  The merge bisects per uniform in a bracket wider than 16
+    LDS windows: the answers equal searchsorted-left and the call stays
+    fast."""
+    import time
+    import torch
+    from paper_1212_1639_amd import pf
+    n = 1 << 22
+    q = np.full(n, 0.5)
+    q[-1] = 1.0
+    u = (np.arange(n) + 0.5) / n
+    qd = torch.tensor(q, dtype=torch.float64, device=dev)
+    ud = torch.tensor(u, dtype=torch.float64, device=dev)
+    pf.debug_search(qd, ud, pf.SEARCH_MERGE)   # warm-up
+    t0 = time.perf_counter()
+    got = pf.debug_search(qd, ud, pf.SEARCH_MERGE).cpu().numpy()
+    dt = time.perf_counter() - t0
+    want = np.searchsorted(q, u, side="left")
+    np.testing.assert_array_equal(got, np.minimum(want, n - 1))
+    print(f"merge over a flat run of {n - 2}: {1e3 * dt:.2f} ms", flush=True)
+    assert dt < 0.05

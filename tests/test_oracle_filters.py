@@ -363,3 +363,23 @@ def test_run_given_ancestors(orc, model):
     bad = other.copy()
     bad[3] = n
     assert orc.run(cfg, y[t0:], state0=st, t0=t0, y_prev=y[t0 - 1], anc_first=bad)["rc"] == -2
+
+
+def test_sv_pl_single_block_draws_target_the_same_posterior(orc, y_sv):
+    """With 24-bit uniforms and systematic resampling, SV-PL takes a slot's
+    five uniforms from one Philox block (the (z3, z4) pair for (alpha, beta)
+    from word 0 and the low bytes of words 1-3); with stratified resampling
+    it uses two blocks.  Both are the same particle-learning filter, so over
+    seeds their log-likelihoods and parameter means agree within Monte Carlo
+    error; draws of the wrong law or dependent normals in the single block
+    would bias the (alpha, beta) draws and with them the filter."""
+    kw = dict(prior_mean=[MU * (1 - PHI), PHI], prior_prec=[1.0, 0.0, 1.0], a_s=2.0, d_s=0.04,
+              **SV0)
+    y = y_sv[:40]
+    one = _runs(orc, orc.SV_PL, 2048, range(24), y, orc.SYSTEMATIC, fp32_words=True, **kw)
+    two = _runs(orc, orc.SV_PL, 2048, range(100, 124), y, orc.STRATIFIED, fp32_words=True, **kw)
+    for col in (None, 2, 3, 4):
+        a = np.array([r["loglik"].sum() if col is None else r["moments"][-1, col] for r in one])
+        b = np.array([r["loglik"].sum() if col is None else r["moments"][-1, col] for r in two])
+        se = np.sqrt(a.var(ddof=1) / a.size + b.var(ddof=1) / b.size)
+        assert abs(a.mean() - b.mean()) < 4 * se, (col, a.mean(), b.mean(), se)
