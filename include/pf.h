@@ -278,6 +278,20 @@ int pf_step_batch(pf_filter* const* filters, int32_t n, const double* y_each);
 int pf_debug_search(const double* cdf_dev, const double* u_dev, int64_t n, int64_t m,
                     int32_t strategy, int32_t* anc_dev, void* hip_stream);
 
+/* pf_debug_search for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and results, but the check flag and the
+ * cut-point table live in a static device array that each GPU holds for
+ * the life of the process (4 MiB + 256 B), so no call allocates or frees.
+ * The table holds at most 2^20 entries: PF_SEARCH_CUTPOINT with
+ * n > 2^20 is PF_EINVAL (the other strategies take any n < 2^31).  The
+ * array of the current device is used (hip_stream must belong to it) and
+ * every call on that device shares it: calls that overlap on one GPU, from
+ * several threads or streams, race.  Synchronises the stream.  Errors as
+ * pf_debug_search, without PF_ENOMEM. */
+int pf_debug_search_noalloc(const double* cdf_dev, const double* u_dev, int64_t n, int64_t m,
+                            int32_t strategy, int32_t* anc_dev, void* hip_stream);
+
 /* Copy the current particles to host memory for small-N tests: the record
  * as pf_fields(model) arrays of N values (float for PF_FP32, double for
  * PF_FP64), followed by N int32 ancestors that produced them (identity when

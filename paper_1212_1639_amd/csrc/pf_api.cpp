@@ -21,6 +21,8 @@ hipError_t launch_scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t 
 hipError_t launch_spacings(int ipt, uint64_t seed, uint32_t t, int64_t n, int32_t num_tiles,
                            double* aggE, TileAB* abE, Totals* totE, double* chunk, hipStream_t s);
 int32_t scan_chunks(int32_t num_tiles);
+hipError_t static_scratch(int32_t** out);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_cut_table(bool fp64, const void* c, const TileAB* ab, int64_t n, int32_t ts,
                             int32_t tiles, int32_t* table, hipStream_t s);
 hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int2* tile_map,
@@ -828,6 +830,33 @@ int pf_debug_search(const double* cdf_dev, const double* u_dev, int64_t n, int64
     hipFree(bad);
     if (table) hipFree(table);
     return rc;
+}
+
+int pf_debug_search_noalloc(const double* cdf_dev, const double* u_dev, int64_t n, int64_t m,
+                            int32_t strategy, int32_t* anc_dev, void* hip_stream) {
+    if (!cdf_dev || n < 1 || n > INT32_MAX) return fail(PF_EINVAL, "need a CDF of 1 <= n < 2^31 entries");
+    if (m < 0 || (m > 0 && (!u_dev || !anc_dev))) return fail(PF_EINVAL, "bad uniforms / output");
+    if (strategy == PF_SEARCH_AUTO) strategy = PF_SEARCH_MERGE;
+    if (strategy < PF_SEARCH_BINARY || strategy > PF_SEARCH_MERGE)
+        return fail(PF_EINVAL, "unknown search strategy");
+    if (strategy == PF_SEARCH_CUTPOINT && n > pf::kStaticCutMax)
+        return fail(PF_EINVAL, "pf_debug_search_noalloc: the cut-point table holds at most 2^20 "
+                               "entries (use pf_debug_search for larger CDFs)");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int32_t* scr = nullptr;
+    hipError_t e = pf::static_scratch(&scr);
+    if (e != hipSuccess) return hip_fail(e, "pf_debug_search_noalloc: static scratch");
+    int32_t* bad = scr;
+    int32_t* table = strategy == PF_SEARCH_CUTPOINT ? scr + pf::kStaticTableOffset : nullptr;
+    // the array keeps the previous call's contents: the flag starts at zero
+    e = pf::launch_fill_i32(bad, 1, 0, s);
+    if (e == hipSuccess) e = pf::launch_search(strategy, cdf_dev, n, u_dev, m, anc_dev, table, bad, s);
+    int32_t hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pf_debug_search_noalloc");
+    if (hbad) return fail(PF_EINVAL, "CDF is decreasing somewhere or not finite");
+    return PF_OK;
 }
 
 int pf_debug_particles(pf_filter* f, void* host_out, size_t bytes, int64_t* t_out) {

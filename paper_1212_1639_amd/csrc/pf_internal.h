@@ -42,6 +42,10 @@ enum StepFlags : int32_t {
 // for more tiles the work-groups' completion count, one atomic per
 // work-group on a single word, costs more than the launch.
 constexpr int32_t kFusedScanMax = 16;
+// pf_debug_search_noalloc: largest CDF its static cut-point table holds, and
+// where the table starts in the static scratch array (after the check flag).
+constexpr int64_t kStaticCutMax = int64_t(1) << 20;
+constexpr int64_t kStaticTableOffset = 64;
 
 // Per-tile output of the CDF scan.  m_* are log-scale shifts, s_* sums of
 // exp(l - m): the tile's exclusive prefix over all earlier tiles (m_ex, s_ex)

@@ -24,6 +24,8 @@
 //     tile with the last ticket forms the totals.
 // The normalised CDF is never materialised.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <math.h>
 #include <stdint.h>
 
@@ -2041,8 +2043,54 @@ __global__ void k_check_cdf(const double* q, int64_t n, int32_t* bad) {
 
 }  // namespace pf
 
+// ------------------------------------------------------------ static scratch
+// Device memory of the search entry point that allocates nothing
+// (pf_debug_search_noalloc): word 0 is the CDF check flag, the cut-point
+// table starts at word kStaticTableOffset (256-byte aligned).  Each GPU the
+// library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (static_scratch below), never through the array's name.
+static __device__ __align__(256) int32_t scratch[pf::kStaticTableOffset + pf::kStaticCutMax];
+
+// p[0 .. n) = v (clears flags without a memset node, so callers may capture it).
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
 // ------------------------------------------------------------ launchers
 namespace pf {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+hipError_t static_scratch(int32_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
 
 using StepFn = void (*)(StepArgs);
 

@@ -32,7 +32,7 @@ EXPORTS = ["pf_fields", "pf_workspace_bytes", "pf_create", "pf_step", "pf_loglik
            "pf_batch_destroy", "pf_step_batch", "pf_debug_search", "pf_debug_particles",
            "pf_timing_start", "pf_timing_read", "pf_autotune", "pf_autotune_batch",
            "pf_copy_particles_async", "pf_checkpoint_bytes", "pf_checkpoint_save",
-           "pf_checkpoint_restore", "pf_batch_bytes"]
+           "pf_checkpoint_restore", "pf_batch_bytes", "pf_debug_search_noalloc"]
 
 
 class PFError(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
         L.pf_destroy.argtypes = [vp]
         L.pf_last_error.restype = ctypes.c_char_p
         L.pf_debug_search.argtypes = [vp, vp, i64, i64, i32, vp, vp]
+        L.pf_debug_search_noalloc.argtypes = [vp, vp, i64, i64, i32, vp, vp]
         L.pf_debug_particles.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(i64)]
         L.pf_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)]
         L.pf_batch_update.argtypes = [vp, ctypes.POINTER(vp), i32]
@@ -112,7 +113,8 @@ def lib():
         for name in ("pf_create", "pf_step", "pf_loglik", "pf_moments", "pf_destroy",
                      "pf_batch_create", "pf_batch_update", "pf_batch_step", "pf_batch_destroy",
                      "pf_step_batch",
-                     "pf_debug_search", "pf_debug_particles", "pf_checkpoint_save",
+                     "pf_debug_search", "pf_debug_search_noalloc", "pf_debug_particles",
+                     "pf_checkpoint_save",
                      "pf_checkpoint_restore"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L

@@ -100,6 +100,8 @@ hipError_t launch_step(int, bool, int, const StepArgs&, int, hipStream_t, bool) 
 hipError_t launch_scan_tiles(double*, int32_t, int64_t, int32_t, TileAB*, int32_t*, Totals*, DevState*, double*, const TileAB*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_spacings(int, uint64_t, uint32_t, int64_t, int32_t, double*, TileAB*, Totals*, double*, hipStream_t) { return hipErrorNoDevice; }
 int32_t scan_chunks(int32_t num_tiles) { return (num_tiles + 1023) / 1024; }
+hipError_t static_scratch(int32_t**) { return hipErrorNoDevice; }
+hipError_t launch_fill_i32(int32_t*, int64_t, int32_t, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_cut_table(bool, const void*, const TileAB*, int64_t, int32_t, int32_t, int32_t*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_batch(int, bool, int, const StepArgs*, const int2*, int32_t, BatchState*, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_batch_map(const int32_t*, int32_t, int2*, hipStream_t) { return hipErrorNoDevice; }
@@ -173,6 +175,8 @@ def test_host_runtime_under_sanitizers(tmp_path):
         assert L.pf_debug_search(None, q, 10, 1, 1, q, None) != 0
         assert L.pf_debug_search(q, None, 10, 1, 1, q, None) != 0
         assert L.pf_debug_search(q, q, 10, 1, 9, q, None) != 0
+        assert L.pf_debug_search_noalloc(q, q, (1 << 20) + 1, 1, pf.SEARCH_CUTPOINT, q, None) != 0
+        assert L.pf_debug_search_noalloc(q, q, 10, 1, pf.SEARCH_BINARY, q, None) == pf.EDEVICE
         y = (ctypes.c_double * 3)(0.1, 0.2, 0.3)
         c = good[0]
         ms = ctypes.c_double()
