@@ -36,8 +36,8 @@ Workloads (all synthetic; data simulated from the model):
               the run count), plus the phase breakdown at 131,072
   ll_pl_batch256  256 independent local-level particle-learning filters, each
               with its own seed and data, N drawn log-uniform in [2^12, 2^18],
-              T = 200, stratified, FP32; stepped together (one persistent
-              launch per step, replayed from a HIP graph) and, for comparison,
+              T = 200, stratified, FP32; stepped together (one launch over
+              all their tiles per step, replayed from a HIP graph) and, for comparison,
               one after the other ("plain")
 """
 from __future__ import annotations
@@ -325,7 +325,7 @@ def run_paper(args, w, pf, torch):
 def measure_batch(args, w, pf, torch, K, W, tune=True):
     """Batched vs plain stepping of many filters of uneven N: the batch's
     common tile size and search chosen by the library's autotuner (when
-    `tune`), then K full cycles of the batch (one persistent launch per
+    `tune`), then K full cycles of the batch (one launch over all tiles per
     step, replayed from a HIP graph) and the same K cycles with every filter
     stepped alone, one after the other.  The first observation of each
     filter (which only weighs) is stepped before the timed region."""

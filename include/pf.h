@@ -219,7 +219,7 @@ const char* pf_last_error(void);
 
 /* ---------------------------------------------------------- batches  */
 /* Many independent filters stepped together (the cycle of Section 3.2 run
- * for all of them at once): per observation, one persistent launch works
+ * for all of them at once): per observation, one launch works
  * through the tiles of every filter in the batch and one launch scans each
  * filter's tiles; the pair is captured once in a HIP graph and replayed per
  * step, its arguments read from a device ring filled ahead of time.  A

@@ -28,7 +28,6 @@ hipError_t launch_cut_table(bool fp64, const void* c, const TileAB* ab, int64_t 
 hipError_t launch_batch(int model, bool fp64, int ipt, const StepArgs* descs, const int2* tile_map,
                         int32_t capacity, BatchState* bs, int grid, hipStream_t s);
 hipError_t launch_batch_map(const int32_t* base, int32_t n_filters, int2* tile_map, hipStream_t s);
-int batch_grid(int model, bool fp64, int ipt);
 hipError_t launch_moments(int model, const double* partials, int32_t num_tiles, int64_t n,
                           int32_t weighted, uint32_t t, const ModelParams& p, DevState* st,
                           hipStream_t s);
@@ -443,7 +442,7 @@ struct pf_filter {
 struct pf_batch {
     std::vector<pf_filter*> fs;
     hipStream_t stream = nullptr;
-    int model = 0, ipt = 0, grid = 0;
+    int model = 0, ipt = 0;
     bool fp64 = false;
     int32_t ring = 0, capacity = 0;
     int64_t total_tiles = 0;
@@ -1054,7 +1053,6 @@ int pf_batch_create(pf_filter* const* filters, int32_t n, int32_t capacity, int3
         pf_batch_destroy(b);
         return hip_fail(e, "pf_batch_create");
     }
-    b->grid = pf::batch_grid(b->model, b->fp64, b->ipt);
     rc = pf_batch_update(b, filters, n);
     if (rc != PF_OK) {
         pf_batch_destroy(b);
@@ -1088,8 +1086,11 @@ int pf_batch_step(pf_batch* b, const double* y, int64_t n_steps) {
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
+            // one work-group per entry of the tile map (those beyond the
+            // members' tiles return at once); a larger map is captured anew
             hipError_t le = pf::launch_batch(b->model, b->fp64, b->ipt, b->d_descs, b->d_map,
-                                             b->capacity, b->d_state, b->grid, cs);
+                                             b->capacity, b->d_state,
+                                             static_cast<int>(b->map_cap), cs);
             e = hipStreamEndCapture(cs, &g);
             if (le != hipSuccess) e = le;
         }

@@ -149,7 +149,7 @@ struct StepArgs {
 // Device-side progress of a batch of filters stepped together.
 struct BatchState {
     uint64_t step;      // steps completed; selects the argument block of the next step
-    uint64_t ticket;    // global tile ticket of the running step
+    uint64_t reserved;  // (unused; keeps the layout the host copies into)
     uint32_t done;      // scan work-groups finished in the running step
     uint32_t ring;      // argument blocks in the ring (steps that can be queued)
     int32_t n_filters;  // current members (argument blocks hold `capacity` entries)

@@ -1164,11 +1164,6 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
 // With 8 items per thread the LDS window already limits residency to three.
 template <int IPT>
 constexpr int step_min_blocks() { return IPT >= 8 ? 3 : 5; }
-// The batched kernel carries the per-filter arguments in registers as well;
-// four resident work-groups per CU measured best for it.
-template <int IPT>
-constexpr int batch_min_blocks() { return IPT >= 8 ? 3 : 4; }
-
 template <int MODEL, typename R, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK, step_min_blocks<IPT>()) void k_step(StepArgs A) {
     __shared__ StepSmem<BLOCK, IPT> sm;
@@ -1183,48 +1178,33 @@ __global__ __launch_bounds__(BLOCK, step_min_blocks<IPT>()) void k_step(StepArgs
     cycle<MODEL, R, BLOCK, IPT>(A, tile, sm);
 }
 
-// Many filters, one cycle each, in one persistent launch: resident
-// work-groups take global tile numbers from a ticket until all tiles of all
-// filters are done.  tile_map[g] = (owner filter f, tile of f) for global
-// tile g; filter f's arguments for step s are descs[(s mod ring) * capacity
-// + f], where s is the batch's device-side step counter (advanced, and the
-// ticket reset, by k_scan_batch), so the same pair of launches can be
-// replayed step after step.  Each work-group asks for its next ticket when
-// it starts a tile, so the atomic's round trip overlaps the tile's work.
+// Many filters, one cycle each, in one launch: work-group g takes global
+// tile g, tile_map[g] = (member f, tile of f); filter f's arguments for
+// step s are descs[(s mod ring) * capacity + f], where s is the batch's
+// device-side step counter (advanced by k_scan_batch), so the same pair of
+// launches can be replayed step after step.  The grid covers the tile map's
+// capacity; work-groups at or beyond the batch's current tile count return
+// at once, so membership can change between replays.  (A persistent grid
+// that took tiles from a ticket held one work-group fewer per CU and paid a
+// dependent ticket-map-descriptor prologue per tile: 12% slower.)
 template <int MODEL, typename R, int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK, batch_min_blocks<IPT>()) void k_step_batch(
+__global__ __launch_bounds__(BLOCK, step_min_blocks<IPT>()) void k_step_batch(
     const StepArgs* __restrict__ descs, const int2* __restrict__ tile_map, BatchState* bs) {
     __shared__ StepSmem<BLOCK, IPT> sm;
+    const int64_t g = blockIdx.x;
+    const int64_t total = uniform64(bs->total_tiles);
+    if (g >= total) return;
     // the batch's state is the same for the whole grid: keep it (and every
     // address derived from it) in scalar registers
     const uint64_t step = static_cast<uint64_t>(uniform64(static_cast<int64_t>(
         __hip_atomic_load(&bs->step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))));
-    const int32_t n_filters = static_cast<int32_t>(uniform32(static_cast<uint32_t>(bs->n_filters)));
-    if (n_filters <= 0) return;
-    const int64_t total = uniform64(bs->total_tiles);
     const uint32_t ring = uniform32(bs->ring);
     const uint32_t capacity = uniform32(static_cast<uint32_t>(bs->capacity));
     const StepArgs* d = descs + (step % ring) * capacity;
-    if (threadIdx.x == 0)
-        sm.lo = static_cast<int64_t>(__hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT));
-    __syncthreads();
-    int64_t g = uniform64(sm.lo);
-    while (g < total) {
-        uint64_t next = 0;
-        if (threadIdx.x == 0)
-            next = __hip_atomic_fetch_add(&bs->ticket, 1ull, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        const int2 owner = tile_map[g];
-        const int32_t f = static_cast<int32_t>(uniform32(static_cast<uint32_t>(owner.x)));
-        const uint32_t tile = uniform32(static_cast<uint32_t>(owner.y));
-        cycle<MODEL, R, BLOCK, IPT>(d[f], tile, sm);
-        // every wave is past the cycle's last use of the shared fields
-        __syncthreads();
-        if (threadIdx.x == 0) sm.lo = static_cast<int64_t>(next);
-        __syncthreads();
-        g = uniform64(sm.lo);
-    }
+    const int2 owner = tile_map[g];
+    const int32_t f = static_cast<int32_t>(uniform32(static_cast<uint32_t>(owner.x)));
+    const uint32_t tile = uniform32(static_cast<uint32_t>(owner.y));
+    cycle<MODEL, R, BLOCK, IPT>(d[f], tile, sm);
 }
 
 // tile_map[base[f] + k] = (f, k) for every tile k of member f (one
@@ -1752,7 +1732,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const double* __restr
 
 // The batch's scans: work-group g scans filters g, g + grid, ... (those that
 // weighted this step); the last work-group to finish advances the batch's
-// step counter and resets its tile ticket.
+// step counter.
 __global__ __launch_bounds__(kTileScanBlock) void k_scan_batch(const StepArgs* __restrict__ descs,
                                                            BatchState* bs) {
     __shared__ uint32_t s_last;
@@ -1791,7 +1771,6 @@ __global__ __launch_bounds__(kTileScanBlock) void k_scan_batch(const StepArgs* _
         s_last = (dn == gridDim.x - 1) ? 1u : 0u;
         if (s_last) {
             __hip_atomic_store(&bs->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bs->ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bs->step, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -2177,31 +2156,6 @@ hipError_t launch_batch_map(const int32_t* base, int32_t n_filters, int2* tile_m
     if (n_filters <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_map, dim3(n_filters), dim3(256), 0, s, base, n_filters, tile_map);
     return hipGetLastError();
-}
-
-// Resident work-groups of the persistent batch kernel on this device.
-int batch_grid(int model, bool fp64, int ipt) {
-    int dev = 0, cus = 256, per = 1;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void* fn = nullptr;
-#define PF_FN(M, RR, I) reinterpret_cast<const void*>(&k_step_batch<M, RR, 256, I>)
-#define PF_SEL(M)                                                                               \
-    fn = fp64 ? (ipt == 1 ? PF_FN(M, double, 1) : ipt == 2 ? PF_FN(M, double, 2)               \
-                 : ipt == 4 ? PF_FN(M, double, 4) : PF_FN(M, double, 8))                       \
-              : (ipt == 1 ? PF_FN(M, float, 1) : ipt == 2 ? PF_FN(M, float, 2)                  \
-                 : ipt == 4 ? PF_FN(M, float, 4) : PF_FN(M, float, 8))
-    switch (model) {
-    case kLLPF: PF_SEL(kLLPF); break;
-    case kLLPL: PF_SEL(kLLPL); break;
-    case kSVPF: PF_SEL(kSVPF); break;
-    case kSVPL: PF_SEL(kSVPL); break;
-    }
-#undef PF_SEL
-#undef PF_FN
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1)
-        per = 1;
-    return cus * per;
 }
 
 // Tile counts up to this use the single-work-group scan; above, the chunked

@@ -284,7 +284,7 @@ class Filter:
 
 
 class Batch:
-    """Filters stepped together (one persistent launch per step, graph-replayed)."""
+    """Filters stepped together (one launch over all their tiles per step, graph-replayed)."""
 
     def __init__(self, filters, ring=64, capacity=0):
         self.filters = list(filters)
