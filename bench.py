@@ -64,17 +64,17 @@ TIMING_EVERY = 8
 # the bench reports null.
 COUNTER_SOURCES = ("pf_kernels.hip", "pf_models.hpp", "pf_internal.h")
 TRAFFIC = {
-    "ll_pl_2p20": dict(fetch_kib=13303.42, write_kib=25100.4, sources="e5554d64c75a16ad"),
-    "sv_pl_2p26": dict(fetch_kib=970259.45, write_kib=1872936.15, sources="e5554d64c75a16ad"),
+    "ll_pl_2p20": dict(fetch_kib=13904.6, write_kib=24964.53, sources="5ea0b179e4b51c36"),
+    "sv_pl_2p26": dict(fetch_kib=970253.72, write_kib=1990645.92, sources="5ea0b179e4b51c36"),
     # one batched step: k_step_batch + k_scan_batch
-    "ll_pl_batch256": dict(fetch_kib=247241.97, write_kib=450399.38, sources="e5554d64c75a16ad"),
+    "ll_pl_batch256": dict(fetch_kib=246843.27, write_kib=458969.67, sources="5ea0b179e4b51c36"),
 }
 # Share of the SIMD cycles the cycle kernel's vector instructions occupy
 # (SQ_INSTS_VALU x 4 cycles per wave instruction over the kernel's clock
 # cycles x 1024 SIMDs), from a counter run of the same kernel sources.
 VALU_ISSUE = {
-    "ll_pl_2p20": dict(share=0.47, valu_per_particle=589, sources="e5554d64c75a16ad"),
-    "sv_pl_2p26": dict(share=0.93, valu_per_particle=623, sources="e5554d64c75a16ad"),
+    "ll_pl_2p20": dict(share=0.49, valu_per_particle=644, sources="5ea0b179e4b51c36"),
+    "sv_pl_2p26": dict(share=0.87, valu_per_particle=572, sources="5ea0b179e4b51c36"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
