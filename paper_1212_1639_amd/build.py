@@ -31,6 +31,10 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
            # packed FP32 instructions are kept out of the device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # a multiply and an add are fused only inside one source expression,
+           # so every kernel that inlines the same step (plain and batched)
+           # rounds it the same way, whatever the code around it
+           "-ffp-contract=on",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:

@@ -337,14 +337,27 @@ __device__ void stage_window(const PrevCdf<R>& P, int64_t w0, int cnt, double fl
         s_last[k] = e >= P.n - 1 ? 1.0 : fma(static_cast<double>(P.c[e]), tb, ta);
     }
     __syncthreads();
-    for (int k = tid; k < cnt; k += BLOCK) {
-        const int64_t g = w0 + k;
-        const int bb = static_cast<int>(g / P.ts - b0);
-        double v = 1.0;
-        if (g < P.n - 1) v = fma(static_cast<double>(P.c[g]), s_tb[bb], s_ta[bb]);
-        double f = floor;
-        for (int q = 0; q < bb; ++q) f = fmax(f, s_last[q]);
-        s_q[k] = fmax(v, f);
+    // four of the thread's entries per round, their loads issued together
+    // (indices clamped to N - 1 keep every load in bounds; entries past cnt
+    // are not stored), so that a window costs few memory latencies
+    constexpr int kBatch = 4;
+    for (int k0 = tid; k0 < cnt; k0 += kBatch * BLOCK) {
+        R cv[kBatch];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) cv[r] = P.c[min(w0 + k0 + r * BLOCK, P.n - 1)];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+            const int k = k0 + r * BLOCK;
+            if (k < cnt) {
+                const int64_t g = w0 + k;
+                const int bb = static_cast<int>(g / P.ts - b0);
+                double v = 1.0;
+                if (g < P.n - 1) v = fma(static_cast<double>(cv[r]), s_tb[bb], s_ta[bb]);
+                double f = floor;
+                for (int q = 0; q < bb; ++q) f = fmax(f, s_last[q]);
+                s_q[k] = fmax(v, f);
+            }
+        }
     }
     __syncthreads();
 }
