@@ -64,17 +64,17 @@ TIMING_EVERY = 8
 # the bench reports null.
 COUNTER_SOURCES = ("pf_kernels.hip", "pf_models.hpp", "pf_internal.h")
 TRAFFIC = {
-    "ll_pl_2p20": dict(fetch_kib=13904.6, write_kib=24964.53, sources="5ea0b179e4b51c36"),
-    "sv_pl_2p26": dict(fetch_kib=970253.72, write_kib=1990645.92, sources="5ea0b179e4b51c36"),
+    "ll_pl_2p20": dict(fetch_kib=14033.9, write_kib=24968.75, sources="2e3df8991466f002"),
+    "sv_pl_2p26": dict(fetch_kib=981529.47, write_kib=1990648.42, sources="2e3df8991466f002"),
     # one batched step: k_step_batch + k_scan_batch
-    "ll_pl_batch256": dict(fetch_kib=246843.27, write_kib=458969.67, sources="5ea0b179e4b51c36"),
+    "ll_pl_batch256": dict(fetch_kib=237993.21, write_kib=442721.52, sources="2e3df8991466f002"),
 }
 # Share of the SIMD cycles the cycle kernel's vector instructions occupy
 # (SQ_INSTS_VALU x 4 cycles per wave instruction over the kernel's clock
 # cycles x 1024 SIMDs), from a counter run of the same kernel sources.
 VALU_ISSUE = {
-    "ll_pl_2p20": dict(share=0.49, valu_per_particle=644, sources="5ea0b179e4b51c36"),
-    "sv_pl_2p26": dict(share=0.87, valu_per_particle=572, sources="5ea0b179e4b51c36"),
+    "ll_pl_2p20": dict(share=0.51, valu_per_particle=654, sources="2e3df8991466f002"),
+    "sv_pl_2p26": dict(share=0.93, valu_per_particle=576, sources="2e3df8991466f002"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
