@@ -314,6 +314,15 @@ __device__ __forceinline__ int lds_lower_bound(const double* s_q, int cnt, doubl
     return lo;
 }
 
+// Tile constants the bracket search already read (the hint tiles of the
+// tile's first and last uniforms) and the first one's last value q, kept
+// in LDS so that the first window over those tiles skips its own loads.
+struct WindowPre {
+    int64_t h[2];  // source tiles, -1: none
+    double ta[2], tb[2];
+    double last0;  // q at tile h[0]'s last element
+};
+
 // Stage q(w0 .. w0+cnt-1) in LDS, non-decreasing.  Inside a tile the stored
 // prefix is non-decreasing and q = A_b + c[k] B_b (one fma, B_b >= 0) keeps
 // that order; across tiles rounding of the affine constants can leave a
@@ -323,20 +332,36 @@ __device__ __forceinline__ int lds_lower_bound(const double* s_q, int cnt, doubl
 // barrier.
 template <int BLOCK, typename R>
 __device__ void stage_window(const PrevCdf<R>& P, int64_t w0, int cnt, double floor, double* s_q,
-                             double* s_ta, double* s_tb, double* s_last) {
+                             double* s_ta, double* s_tb, double* s_last,
+                             const WindowPre* pre = nullptr) {
     const int tid = threadIdx.x;
     const int64_t b0 = w0 / P.ts, b1 = (w0 + cnt - 1) / P.ts;
     const int nb = static_cast<int>(b1 - b0 + 1);
-    for (int k = tid; k < nb; k += BLOCK) {
-        double ta, tb;
-        P.tile_ab(b0 + k, ta, tb);
-        s_ta[k] = ta;
-        s_tb[k] = tb;
-        // the tile's last element inside the window
-        const int64_t e = min(w0 + cnt - 1, (b0 + k + 1) * P.ts - 1);
-        s_last[k] = e >= P.n - 1 ? 1.0 : fma(static_cast<double>(P.c[e]), tb, ta);
+    // a window over one preloaded tile, or over the two consecutive
+    // preloaded tiles, needs no loads of its own (and no barrier for them)
+    int pa = -1;
+    if (pre && nb <= 2) {
+        if (b0 == pre->h[0]) pa = 0;
+        else if (nb == 1 && b0 == pre->h[1]) pa = 1;
+        if (nb == 2 && !(pa == 0 && b1 == pre->h[1])) pa = -1;
     }
-    __syncthreads();
+    if (pa < 0) {
+        for (int k = tid; k < nb; k += BLOCK) {
+            double ta, tb;
+            P.tile_ab(b0 + k, ta, tb);
+            s_ta[k] = ta;
+            s_tb[k] = tb;
+            // the tile's last element inside the window
+            const int64_t e = min(w0 + cnt - 1, (b0 + k + 1) * P.ts - 1);
+            s_last[k] = e >= P.n - 1 ? 1.0 : fma(static_cast<double>(P.c[e]), tb, ta);
+        }
+        __syncthreads();
+    }
+    // (a window of two preloaded tiles: the first tile's last element lies
+    // below the window's end, so below N - 1, and its q is pre->last0)
+    const double* ta_of = pa < 0 ? s_ta : pre->ta + pa;
+    const double* tb_of = pa < 0 ? s_tb : pre->tb + pa;
+    const double* last_of = pa < 0 ? s_last : &pre->last0;
     // four of the thread's entries per round, their loads issued together
     // (indices clamped to N - 1 keep every load in bounds; entries past cnt
     // are not stored), so that a window costs few memory latencies
@@ -352,9 +377,9 @@ __device__ void stage_window(const PrevCdf<R>& P, int64_t w0, int cnt, double fl
                 const int64_t g = w0 + k;
                 const int bb = static_cast<int>(g / P.ts - b0);
                 double v = 1.0;
-                if (g < P.n - 1) v = fma(static_cast<double>(cv[r]), s_tb[bb], s_ta[bb]);
+                if (g < P.n - 1) v = fma(static_cast<double>(cv[r]), tb_of[bb], ta_of[bb]);
                 double f = floor;
-                for (int q = 0; q < bb; ++q) f = fmax(f, s_last[q]);
+                for (int q = 0; q < bb; ++q) f = fmax(f, last_of[q]);
                 s_q[k] = fmax(v, f);
             }
         }
@@ -508,6 +533,7 @@ struct StepSmem {
     double q[WIN];           // staged CDF window; reused for the scan
     int cut[kCutMax];        // cut-point table (CDFs of up to kCutMax entries)
     double ta[8], tb[8];     // per-tile affine constants of the window
+    WindowPre pre;           // the bracket's tile constants
     double last[8];          // each window tile's last value
     double red[NW * 16];     // reductions
     int64_t lo, hi;
@@ -679,6 +705,14 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                         P.tile_ab(h, ta, tb);
                         G<const R>* samp = gp(static_cast<const R*>(A.samp_in));
                         const double qs = fma(static_cast<double>(samp[h * kSegments + lane]), tb, ta);
+                        // (kept for the first window: the tile's constants,
+                        // and the last segment's end, which is the tile's end)
+                        if (lane == 0) {
+                            sm.pre.h[wave] = h;
+                            sm.pre.ta[wave] = ta;
+                            sm.pre.tb[wave] = tb;
+                        }
+                        if (wave == 0 && lane == kSegments - 1) sm.pre.last0 = qs;
                         const uint64_t mask = __ballot(qs >= us);
                         const int f = mask ? __ffsll(static_cast<long long>(mask)) - 1 : kSegments;
                         if (wave == 0) {
@@ -692,6 +726,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                         a = min(max(a, int64_t(0)), n - 1);
                     } else {
                         a = wave_search(P, us, int64_t(0), n - 1);
+                        if (lane == 0) sm.pre.h[wave] = -1;
                     }
                     if (lane == 0) {
                         if (wave == 0) sm.lo = a; else sm.hi = a;
@@ -716,7 +751,8 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 double floor = -INFINITY;
                 for (int64_t w0 = a_lo; w0 <= a_hi; w0 += WIN) {
                     const int cnt = static_cast<int>(min(static_cast<int64_t>(WIN), a_hi - w0 + 1));
-                    stage_window<BLOCK>(P, w0, cnt, floor, sm.q, sm.ta, sm.tb, sm.last);
+                    stage_window<BLOCK>(P, w0, cnt, floor, sm.q, sm.ta, sm.tb, sm.last,
+                                        w0 == a_lo ? &sm.pre : nullptr);
                     const bool last = (w0 + cnt - 1 == a_hi);
                     const double top = sm.q[cnt - 1];
                     const bool first = (w0 == a_lo);
