@@ -686,14 +686,23 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 // tiles of CDF positions j0/N and (j0+TS)/N (one tile of slack
                 // either side for rounding); otherwise search the whole CDF.
                 const bool indexed = A.scan == kScanTiles;
+                // (the tile's first uniform is thread 0's first; the last one
+                // takes a Philox block only where the scheme draws per slot)
+                const double u0 = __shfl(u[0], 0);
                 if (wave == 0 || wave == 1) {
                     const int64_t js = wave == 0 ? j0 : jlast;
-                    const double us =
-                        sorted_mult ? (wave == 0 ? sm.u_first : sm.u_last)
-                                    : resample_uniform<kExact>(
-                                          A.scheme, js, n, inv_n,
-                                          philox(A.seed, static_cast<uint32_t>(js), A.t, kStep, 0).w0,
-                                          u_sys);
+                    double us;
+                    if (sorted_mult) {
+                        us = wave == 0 ? sm.u_first : sm.u_last;
+                    } else if (wave == 0) {
+                        us = u0;
+                    } else {
+                        const uint32_t wj = A.scheme == kSystematicScheme
+                                                ? 0u
+                                                : philox(A.seed, static_cast<uint32_t>(js), A.t,
+                                                         kStep, 0).w0;
+                        us = resample_uniform<kExact>(A.scheme, js, n, inv_n, wj, u_sys);
+                    }
                     int64_t a;
                     if (indexed) {
                         // the hint names the source tile of CDF position js/N;

@@ -156,3 +156,29 @@ def test_batch_errors(pf):
     b.close()
     for f in (f1, f2, f3):
         f.close()
+
+
+def test_large_filter_alone_batched_alone(pf):
+    # a filter of more than 4096 tiles (its own tile scan runs in chunks, the
+    # batch's in one work-group per member) stepped alone, then in a batch,
+    # then alone again, equals the same filter stepped alone throughout
+    sizes = [4097 * 256 + 5, 3000]
+    T = 7
+    y = _data("ll_pl", 2, T)
+    print(f"alone / batched / alone sizes={sizes}", flush=True)
+    ref = _make(pf, "ll_pl", sizes[:1], "stratified", True)[0]
+    f, g = _make(pf, "ll_pl", sizes, "stratified", True)
+    ref.step(y[:, 0])
+    f.step(y[:3, 0])
+    g.step(y[:3, 1])
+    batch = pf.Batch([f, g])
+    batch.step(y[3:5])
+    batch.close()
+    f.step(y[5:, 0])
+    la, ra, aa, ta = _state(ref)
+    lb, rb, ab_, tb = _state(f)
+    assert ta == tb and la == lb
+    np.testing.assert_array_equal(aa, ab_)
+    np.testing.assert_array_equal(ra, rb)
+    for h in (ref, f, g):
+        h.close()

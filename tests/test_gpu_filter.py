@@ -76,6 +76,10 @@ CASES = [
     ("sv_pf", 16 * 1024 + 1, "multinomial", "cutpoint", 4, 8, "tiles"),
     ("sv_pl", 5000, "multinomial", "auto", 2, 12, "tiles"),
     ("ll_pf", 9000, "multinomial", "cutpoint", 8, 10, "tiles"),
+    # more than 4096 tiles: the tile scan runs in chunks (three launches)
+    ("ll_pf", 4096 * 256 + 300, "stratified", "merge", 1, 4, "tiles"),
+    ("sv_pf", 4096 * 256 + 1, "systematic", "merge", 1, 3, "tiles"),
+    ("ll_pl", 4097 * 256, "stratified", "merge", 1, 3, "tiles"),
     # double-precision SV-PL at 4 items per thread: switched off (refused)
     pytest.param("sv_pl", 16 * 1024, "systematic", "merge", 4, 8, "tiles", marks=SV_PL_FP64_IPT4_OFF),
     pytest.param("sv_pl", 8 * 1024, "systematic", "merge", 4, 8, "lookback", marks=SV_PL_FP64_IPT4_OFF),
