@@ -119,9 +119,11 @@ WORKLOADS = {
                        # what this record layout moves: x + 5 per-particle
                        # statistics (the shape and L00 are per filter)
                        record_bytes_per_particle=2 * 24 + 8),
+    # (a latency-bound filter of one to four tiles: its tile size and search
+    # are chosen by pf_autotune on the run's own observations)
     "ll_pf_1024": dict(model="ll_pf", n=1024, T=100, scheme="multinomial", fp32=False,
                        params=dict(x0_mean=0.0, x0_var=10.0, sigma_v2=1.0, sigma_w2=0.1),
-                       bytes_per_particle=2 * 8 + 16),
+                       bytes_per_particle=2 * 8 + 16, autotune=True),
     "served_mix": dict(model="mix", n=None, T=None, scheme="mixed", fp32=True, served=True,
                        rate=200.0, duration=30.0, bytes_per_particle=None),
     # the paper's experiment (Section 4, Tables 2 and 3): particle learning on
@@ -587,6 +589,11 @@ def main():
                          items_per_thread=args.items_per_thread, **w["params"])
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    tuned = None
+    if w.get("autotune") and not args.items_per_thread:
+        pf.autotune(cfg, y[:K + 1], stream=stream)
+        tuned = {"items_per_thread": cfg.items_per_thread, "strategy": cfg.strategy,
+                 "lookback_scan": bool(cfg.flags & pf.FLAG_LOOKBACK_SCAN)}
 
     if W > 0:
         warm = pf.Filter(cfg, stream=stream)
@@ -652,6 +659,8 @@ def main():
         "loglik": loglik,
         "moments": [float(v) for v in mom],
     }
+    if tuned is not None:
+        out["config"]["autotuned"] = tuned
     out["latency"] = step_latency(pf, cfg, y, stream, torch, min(K, LATENCY_STEPS))
     if args.workload == "sv_pl_2p26" and not args.no_batch:
         wb = WORKLOADS["ll_pl_batch256"]
@@ -675,7 +684,15 @@ def step_latency(pf, cfg, y, stream, torch, steps):
     first weighting) are left out."""
     res = {"steps": max(0, steps - 2)}
     for form in ("plain", "graph"):
-        f = pf.Filter(cfg, stream=stream)
+        if form == "graph" and cfg.flags & pf.FLAG_LOOKBACK_SCAN:
+            # a batch steps its members with the tile scan: the one-filter
+            # graph runs the same filter with it
+            c = pf.Config.from_buffer_copy(cfg)
+            c.flags &= ~pf.FLAG_LOOKBACK_SCAN
+            f = pf.Filter(c, stream=stream)
+            res["graph_scan"] = "tiles"
+        else:
+            f = pf.Filter(cfg, stream=stream)
         b = pf.Batch([f]) if form == "graph" else None
         lat = []
         for k in range(steps):
