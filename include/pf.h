@@ -192,7 +192,7 @@ int pf_step(pf_filter* f, const double* y, int64_t n_obs);
  * PF_EDEVICE (also when a filter of at most 16 tiles, whose tile scan runs
  * in the cycle kernel's last work-group, found a tile's sums missing after
  * its bounded wait; sticky like PF_EDEGENERATE). */
-int pf_loglik(pf_filter* f, double* out);
+int pf_loglik(const pf_filter* f, double* out);
 
 /* Synchronise and return posterior statistics of the latest time step in
  * out[0..n-1], n = the model's count (PF_LL_PF, PF_SV_PF: 3; PF_LL_PL: 6;

@@ -297,6 +297,8 @@ struct pf_filter {
 
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+    template <typename T>
+    const T* at(size_t off) const { return reinterpret_cast<const T*>(ws + off); }
 
     pf::StepArgs args() {
         pf::StepArgs a{};
@@ -537,7 +539,7 @@ int pf_step(pf_filter* f, const double* y, int64_t n_obs) {
     return PF_OK;
 }
 
-int pf_loglik(pf_filter* f, double* out) {
+int pf_loglik(const pf_filter* f, double* out) {
     if (!f || !out) return fail(PF_EINVAL, "NULL argument");
     pf::DevState st;
     hipError_t e = hipMemcpyAsync(&st, f->at<pf::DevState>(f->L.state), sizeof(st),
