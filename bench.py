@@ -276,13 +276,16 @@ def run_paper(args, w, pf, torch):
         breakdown["store"] = breakdown["cycles_and_store"] - breakdown["cycles"]
     # the multinomial cycle with the paper's cut-point search (the library's
     # default: its table in LDS up to 2048 particles, in device memory above)
-    # against bisection per slot, and stratified resampling with the merge
-    # search for reference: device time per cycle, no store
+    # against bisection per slot and against sorted multinomial (the same
+    # law, its uniforms formed in order from exponential spacings, searched
+    # by the merge at 2 items per thread), and stratified resampling with the
+    # merge search for reference: device time per cycle, no store
     search_ms = {}
     for n in [m for m in (131072, 1048576, 8388608) if m in sizes]:
         row = {}
         for name, scheme, strat in (("cutpoint", pf.MULTINOMIAL, pf.SEARCH_CUTPOINT),
                                     ("bisection", pf.MULTINOMIAL, pf.SEARCH_BINARY),
+                                    ("sorted_merge", pf.SORTED_MULTINOMIAL, pf.SEARCH_MERGE),
                                     ("stratified_merge", pf.STRATIFIED, pf.SEARCH_MERGE)):
             c = pf.make_config(w["model"], n, 1, scheme=scheme, precision=pf.FP32, strategy=strat,
                                **w["params"])

@@ -71,10 +71,9 @@ enum pf_model { PF_LL_PF = 0, PF_LL_PL = 1, PF_SV_PF = 2, PF_SV_PL = 3 };
  * -log U_0 .. -log U_j, U_i from slot i's multinomial word, i = 0..N), so
  * that slots receive ancestors in increasing order and the search merges
  * like the stratified scheme; the offspring counts are multinomial exactly.
- * Sorted multinomial needs the tile scan and is not batched.
- * PF_SORTED_MULTINOMIAL IS CURRENTLY SWITCHED OFF: configurations that use
- * it are refused with PF_EINVAL (its first GPU run faulted; the cause is
- * not yet found). */
+ * Sorted multinomial needs the tile scan and is not batched; in PF_FP32 it
+ * runs at 1, 2 or 8 items per thread (library choice 2; 4 is refused with
+ * PF_EINVAL). */
 enum pf_scheme {
     PF_MULTINOMIAL = 0,
     PF_STRATIFIED = 1,

@@ -58,11 +58,12 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr size_t kAlign = 256;
-// Sorted multinomial resampling (exponential spacings) is switched off: its
-// first GPU run faulted (double precision, stochastic-volatility particle
-// learning, 5000 particles, 4 items per thread) after three smaller cases
-// passed, and no cause has been shown yet.
-constexpr bool kSortedMultinomial = false;
+// Sorted multinomial resampling (exponential spacings).  Its first GPU run
+// faulted in the double-precision SV-PL kernel of 4 items per thread, which
+// stays refused (it gives wrong weights under every scheme).  The single-
+// precision kernels of 4 items per thread carry no sorted-multinomial code:
+// the library picks 2 items there and refuses an explicit 4.
+constexpr bool kSortedMultinomial = true;
 constexpr int64_t kCutMax = 2048;  // largest CDF with an in-LDS cut-point table
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -99,6 +100,7 @@ bool switched_off_ipt(const pf_config& c, int ipt) {
 int choose_ipt(const pf_config& c) {
     if (c.items_per_thread) return c.items_per_thread;
     if (switched_off_ipt(c, 4)) return 1;
+    if (c.scheme == PF_SORTED_MULTINOMIAL && c.precision == PF_FP32) return 2;
     // measured on MI355X: 4 items per thread (with 5 resident work-groups
     // per CU) beats 2 and 8 from 2^20 to 2^26 particles
     return 4;
@@ -147,6 +149,9 @@ int plan(const pf_config* c, Layout* L) {
     if (switched_off_ipt(*c, ipt))
         return fail(PF_EINVAL, "double-precision PF_SV_PL with 4 items per thread is switched off "
                                "(wrong weights whose cause has not been found); use 1, 2 or 8");
+    if (c->scheme == PF_SORTED_MULTINOMIAL && c->precision == PF_FP32 && ipt == 4)
+        return fail(PF_EINVAL, "sorted multinomial in PF_FP32 runs at 1, 2 or 8 items per thread "
+                               "(the 4-item single-precision kernels carry no code for it)");
     if (!finite_all({c->x0_mean, c->x0_var}) || !(c->x0_var > 0))
         return fail(PF_EINVAL, "x0_var must be finite and > 0");
     switch (c->model) {

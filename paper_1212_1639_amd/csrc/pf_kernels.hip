@@ -456,9 +456,13 @@ __device__ __forceinline__ double resample_uniform(int32_t scheme, int64_t j, in
 }
 
 // ------------------------------------------------------------ sorted multinomial
-// Compiled out of the step kernels while the host refuses the scheme: its
-// first GPU run ended in a memory fault whose cause has not been found.
-constexpr bool kSortedKernels = false;
+// The branch is compiled into the cycle kernels of every tile size in double
+// precision and of 1, 2 and 8 items per thread in single precision; the
+// single-precision kernels of 4 items per thread (the large-filter and batch
+// kernels) carry none of its code, and the host does not give them the
+// scheme.
+template <typename R, int IPT>
+constexpr bool sorted_kernel() { return sizeof(R) == 8 || IPT != 4; }
 
 // Exponential spacing -log U of a resampling word (double precision).
 __device__ __forceinline__ double spacing(uint32_t w0) { return -log(unit64(w0)); }
@@ -635,7 +639,7 @@ __device__ __forceinline__ void cycle(const StepArgs& A, uint32_t tile,
                 u_sys = unit64(philox(A.seed, 0, A.t, kSystematic, 0).w0);
             double u[IPT];
             const int64_t jlast = min(j0 + TS, n) - 1;
-            const bool sorted_mult = kSortedKernels && A.scheme == kSortedMultinomial;
+            const bool sorted_mult = sorted_kernel<R, IPT>() && A.scheme == kSortedMultinomial;
             // the uniforms rise with the slot (a thread's own ones too)
             const bool sorted_u = A.scheme != kMultinomial;
             if (sorted_mult) {

@@ -102,10 +102,21 @@ def test_workspace_bytes_and_validation(pf):
     f32 = pf.make_config("sv_pl", 1 << 14, 1, scheme=pf.SYSTEMATIC, precision=pf.FP32,
                          items_per_thread=4, **svp)
     assert pf.workspace_bytes(f32) > 0
-    # sorted multinomial is switched off: refused with a message that says so
+    # sorted multinomial: accepted in FP64 at any tile size and in FP32 at 1,
+    # 2 and 8 items per thread, never with the look-back scan
     sm = pf.make_config("ll_pf", 1 << 16, 1, scheme=pf.SORTED_MULTINOMIAL, sigma_v2=1,
                         sigma_w2=0.1, x0_var=10)
-    with pytest.raises(pf.PFError, match="switched off"):
+    assert pf.workspace_bytes(sm) > 0
+    for ipt, ok in ((0, True), (2, True), (4, False)):
+        s32 = pf.make_config("ll_pf", 1 << 16, 1, scheme=pf.SORTED_MULTINOMIAL, precision=pf.FP32,
+                             items_per_thread=ipt, sigma_v2=1, sigma_w2=0.1, x0_var=10)
+        if ok:
+            assert pf.workspace_bytes(s32) > 0
+        else:
+            with pytest.raises(pf.PFError, match="sorted multinomial"):
+                pf.workspace_bytes(s32)
+    sm.flags = pf.FLAG_LOOKBACK_SCAN
+    with pytest.raises(pf.PFError, match="tile scan"):
         pf.workspace_bytes(sm)
     cfg = pf.make_config("sv_pl", 100, 1, prior_prec=[1.0, 2.0, 1.0], a_s=2, d_s=0.04, x0_var=1)
     with pytest.raises(pf.PFError, match="positive definite"):

@@ -30,11 +30,6 @@ def _strategy(pf, name):
             "merge": pf.SEARCH_MERGE}[name]
 
 
-SORTED_OFF = pytest.mark.skip(
-    reason="sorted multinomial is switched off: its first GPU run (double precision, "
-           "stochastic-volatility particle learning, N = 5000, 4 items per thread) ended in a "
-           "memory fault whose cause has not been found on the CPU")
-
 SV_PL_FP64_IPT4_OFF = pytest.mark.skip(
     reason="double-precision SV-PL with 4 items per thread is switched off: it gave wrong "
            "weights from the first resampling on (and its one sorted-multinomial run faulted "
@@ -83,14 +78,17 @@ CASES = [
     # double-precision SV-PL at 4 items per thread: switched off (refused)
     pytest.param("sv_pl", 16 * 1024, "systematic", "merge", 4, 8, "tiles", marks=SV_PL_FP64_IPT4_OFF),
     pytest.param("sv_pl", 8 * 1024, "systematic", "merge", 4, 8, "lookback", marks=SV_PL_FP64_IPT4_OFF),
-    # sorted multinomial (order statistics from exponential spacings): switched
-    # off after the fourth case below faulted the GPU on its first run
-    pytest.param("ll_pf", 3000, "sorted_multinomial", "merge", 1, 20, "tiles", marks=SORTED_OFF),
-    pytest.param("ll_pf", 700, "sorted_multinomial", "auto", 1, 12, "tiles", marks=SORTED_OFF),
-    pytest.param("ll_pl", 2049, "sorted_multinomial", "auto", 2, 20, "tiles", marks=SORTED_OFF),
-    pytest.param("sv_pl", 5000, "sorted_multinomial", "merge", 4, 12, "tiles", marks=SORTED_OFF),
-    pytest.param("sv_pf", 20000, "sorted_multinomial", "binary", 8, 8, "tiles", marks=SORTED_OFF),
-    pytest.param("ll_pl", 100000, "sorted_multinomial", "merge", 4, 6, "tiles", marks=SORTED_OFF),
+    # sorted multinomial (order statistics from exponential spacings); its
+    # first GPU run faulted in the fourth case, in the switched-off double-
+    # precision SV-PL kernel of 4 items per thread, which stays refused
+    ("ll_pf", 3000, "sorted_multinomial", "merge", 1, 20, "tiles"),
+    ("ll_pf", 700, "sorted_multinomial", "auto", 1, 12, "tiles"),
+    ("ll_pl", 2049, "sorted_multinomial", "auto", 2, 20, "tiles"),
+    pytest.param("sv_pl", 5000, "sorted_multinomial", "merge", 4, 12, "tiles", marks=SV_PL_FP64_IPT4_OFF),
+    ("sv_pl", 5000, "sorted_multinomial", "merge", 2, 12, "tiles"),
+    ("sv_pf", 20000, "sorted_multinomial", "binary", 8, 8, "tiles"),
+    ("ll_pl", 100000, "sorted_multinomial", "merge", 4, 6, "tiles"),
+    ("ll_pf", 4096 * 256 + 300, "sorted_multinomial", "merge", 1, 3, "tiles"),
 ]
 
 
@@ -131,7 +129,7 @@ def _rel_err(a, b, sd):
 
 FP32_MODELS = [("ll_pl", "stratified"), ("ll_pf", "stratified"), ("sv_pl", "systematic"),
                ("sv_pf", "systematic"),
-               pytest.param("ll_pl", "sorted_multinomial", marks=SORTED_OFF)]
+               ("ll_pl", "sorted_multinomial")]
 
 
 @pytest.mark.parametrize("model,scheme", FP32_MODELS)
