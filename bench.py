@@ -64,17 +64,17 @@ TIMING_EVERY = 8
 # the bench reports null.
 COUNTER_SOURCES = ("pf_kernels.hip", "pf_models.hpp", "pf_internal.h")
 TRAFFIC = {
-    "ll_pl_2p20": dict(fetch_kib=13994.11, write_kib=24967.1, sources="d4cef2068bba9e9d"),
-    "sv_pl_2p26": dict(fetch_kib=981876.19, write_kib=1990648.61, sources="d4cef2068bba9e9d"),
+    "ll_pl_2p20": dict(fetch_kib=14074.5, write_kib=24964.72, sources="46bb7911f8dcef05"),
+    "sv_pl_2p26": dict(fetch_kib=981147.61, write_kib=1990648.42, sources="46bb7911f8dcef05"),
     # one batched step: k_step_batch + k_scan_batch
-    "ll_pl_batch256": dict(fetch_kib=238526.27, write_kib=442728.46, sources="d4cef2068bba9e9d"),
+    "ll_pl_batch256": dict(fetch_kib=239371.0, write_kib=442723.31, sources="46bb7911f8dcef05"),
 }
 # Share of the SIMD cycles the cycle kernel's vector instructions occupy
 # (SQ_INSTS_VALU x 4 cycles per wave instruction over the kernel's clock
 # cycles x 1024 SIMDs), from a counter run of the same kernel sources.
 VALU_ISSUE = {
-    "ll_pl_2p20": dict(share=0.52, valu_per_particle=647, sources="d4cef2068bba9e9d"),
-    "sv_pl_2p26": dict(share=0.95, valu_per_particle=570, sources="d4cef2068bba9e9d"),
+    "ll_pl_2p20": dict(share=0.51, valu_per_particle=647, sources="46bb7911f8dcef05"),
+    "sv_pl_2p26": dict(share=0.94, valu_per_particle=570, sources="46bb7911f8dcef05"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
