@@ -150,11 +150,15 @@ def test_batch_errors(pf):
         pf.Batch([f1, f1])
     with pytest.raises(pf.PFError, match="tile scan"):
         pf.Batch([f1, f3])
+    f4 = pf.Filter(C.pf_config(pf, "ll_pl", 3000, 1, "stratified", False, ipt=4))
+    f5 = pf.Filter(C.pf_config(pf, "ll_pl", 3000, 2, "sorted_multinomial", False, ipt=4))
+    with pytest.raises(pf.PFError, match="stepped alone"):
+        pf.Batch([f4, f5])
     b = pf.Batch([f1])
     with pytest.raises(pf.PFError, match="not finite"):
         b.step(np.array([[np.inf]]))
     b.close()
-    for f in (f1, f2, f3):
+    for f in (f1, f2, f3, f4, f5):
         f.close()
 
 
