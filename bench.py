@@ -248,7 +248,7 @@ def run_paper(args, w, pf, torch):
     if n in sizes:
         c = pf.make_config(w["model"], n, 1, scheme=pf.MULTINOMIAL, precision=pf.FP32,
                            **w["params"])
-        ph = {"initialize": [], "cycles": [], "cycles_and_store": []}
+        ph = {"initialize": [], "cycles": [], "cycles_and_store": [], "cycle_kernel": []}
         for r in range(runs + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -268,12 +268,24 @@ def run_paper(args, w, pf, torch):
             torch.cuda.synchronize()
             t4 = time.perf_counter()
             f.close()
+            # the fused cycle kernel alone (resampling, propagation, weights
+            # and the in-tile CDF), every launch bracketed by events
+            f = pf.Filter(c, stream=stream)
+            f.timing_start(T, 1)
+            f.step(y)
+            stream.synchronize()
+            kern_ms, _ = f.timing_read()
+            f.close()
             if r:
                 ph["initialize"].append(t1 - t0)
                 ph["cycles"].append(t2 - t1)
                 ph["cycles_and_store"].append(t4 - t3)
+                ph["cycle_kernel"].append(kern_ms * 1e-3)
         breakdown = {k: _median5(v) * 1e3 for k, v in ph.items()}
         breakdown["store"] = breakdown["cycles_and_store"] - breakdown["cycles"]
+        # the rest of the cycles: the CDF's tile scan, the cut-point table
+        # (multinomial above one LDS window) and the gaps between launches
+        breakdown["cdf_scan_cut_table_and_gaps"] = breakdown["cycles"] - breakdown["cycle_kernel"]
     # the multinomial cycle with the paper's cut-point search (the library's
     # default: its table in LDS up to 2048 particles, in device memory above)
     # against bisection per slot and against sorted multinomial (the same
