@@ -144,7 +144,9 @@ typedef struct pf_config {
     int32_t items_per_thread; /* 0 = library choice, else one of 1, 2, 4, 8
                                  (4 is refused, PF_EINVAL, for PF_SV_PL in
                                  PF_FP64: switched off, its kernel gave wrong
-                                 weights; the library choice there is 1)      */
+                                 weights; the library choice there is 1; and
+                                 for PF_SORTED_MULTINOMIAL in PF_FP32, whose
+                                 library choice is 2)                         */
     int32_t flags;            /* bitwise OR of PF_FLAG_*; other bits must be 0  */
     double x0_mean, x0_var;   /* prior of x_0                                  */
     double sigma_v2, sigma_w2;/* PF_LL_PF: known variances                     */
