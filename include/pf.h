@@ -224,10 +224,7 @@ const char* pf_last_error(void);
  * through the tiles of every filter in the batch and one launch scans each
  * filter's tiles; the pair is captured once in a HIP graph and replayed per
  * step, its arguments read from a device ring filled ahead of time.  A
- * filter's results are the same as when it is stepped alone, bit for bit,
- * for filters of at most 4096 tiles; a larger filter's tiles are scanned
- * in a different order in the batch (one work-group instead of chunks), so
- * its CDF may differ from the one it has alone in the last bits. */
+ * filter's results are the same as when it is stepped alone, bit for bit. */
 typedef struct pf_batch pf_batch;
 
 /* Group n >= 1 distinct filters of one model, precision and

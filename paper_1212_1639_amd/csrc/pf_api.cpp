@@ -326,6 +326,7 @@ struct pf_filter {
         a.ab_in = at<pf::TileAB>(L.ab);
         a.hint_in = at<int32_t>(L.hint);
         a.agg_out = at<double>(L.agg);
+        a.chunk = at<double>(L.chunk);
         a.abE = L.spacings ? at<pf::TileAB>(L.abE) : nullptr;
         a.cut_in = L.cut_global ? at<int32_t>(L.cut) : nullptr;
         a.p = mp;

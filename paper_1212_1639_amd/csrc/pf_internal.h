@@ -135,6 +135,8 @@ struct StepArgs {
     TileInfo* tiles_out;
     Totals* tot_out;
     double* agg_out;            // tile-scan: this step's (m_b, s_b) per tile
+    double* chunk;              // chunked tile scan (above 4096 tiles): chunk
+                                //   aggregates and prefixes, 3G + 1 doubles
     TileAB* ab_out;             // tile-scan outputs (the arrays ab_in / hint_in
     int32_t* hint_out;          //   point to, read by the next step)
     uint64_t* status;

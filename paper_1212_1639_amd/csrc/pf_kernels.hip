@@ -1361,7 +1361,7 @@ __global__ __launch_bounds__(256) void k_cut_table(CutEnvelope<R> E, int32_t* __
 }
 
 // ------------------------------------------------------------ tile scan
-// One work-group of 1024 threads turns the tiles' (m_b, s_b) into
+// The tile scan turns the tiles' (m_b, s_b) into
 //   A_b = sum_{b' < b} s_b' e^{m_b' - M} / S  (non-decreasing),
 //   B_b = e^{m_b - M} / S,
 // with M = max_b m_b taken first, so that each tile costs one exponential
@@ -1369,8 +1369,10 @@ __global__ __launch_bounds__(256) void k_cut_table(CutEnvelope<R> E, int32_t* __
 // (fixed order: the result does not depend on timing); adds M + log(S / n)
 // to the log-likelihood; and writes hint[h] = the tile whose range
 // [A_b, A_{b+1}) holds the CDF position h * ts / n, for h = 0..tiles, where
-// the next cycle's tile h starts its search for sorted uniforms.  The
-// tiles' maxima are overwritten (agg[2b] becomes e^{m_b - M}).
+// the next cycle's tile h starts its search for sorted uniforms.  Up to
+// 4096 tiles one work-group does it all; above, three launches over chunks
+// of kScanBlock tiles (or one work-group that does the same arithmetic, in
+// a batch).  The (m_b, s_b) pairs are only read.
 constexpr int kScanBlock = 1024;
 
 // The single-work-group tile scan: up to kTileScanBlock * kTileScanPer
@@ -1520,101 +1522,14 @@ __device__ __forceinline__ void scan_tiles_regs(const double* agg, int32_t num_t
                                                  s_red, s_first);
 }
 
-__device__ __forceinline__ void scan_tiles(double* agg, int32_t num_tiles, int64_t n, int32_t ts,
-                                           TileAB* ab, int32_t* hint, Totals* tot, DevState* st) {
-    if (num_tiles <= kTileScanBlock * kTileScanPer) {
-        scan_tiles_regs(agg, num_tiles, n, ts, ab, hint, tot, st);
-        return;
-    }
-    constexpr int NW = kTileScanBlock / kWave;
-    __shared__ double s_red[NW], s_top[NW];
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const int T = num_tiles;
-    const int per = (T + kTileScanBlock - 1) / kTileScanBlock;
-    const int b0 = min(T, tid * per), b1 = min(T, b0 + per);
-    // 1. M = max_b m_b
-    double mx = -INFINITY;
-    for (int b = b0; b < b1; ++b) mx = fmax(mx, agg[2 * b]);
-    mx = wave_max(mx);
-    if (lane == 0) s_red[wave] = mx;
-    __syncthreads();
-    double M = -INFINITY;
-    for (int q = 0; q < NW; ++q) M = fmax(M, s_red[q]);
-    __syncthreads();
-    // 2. e_b = e^{m_b - M} (one exponential per tile; kept in agg[2b]) and
-    //    the chunk's sum of w_b = s_b e_b, in tile order
-    double part = 0.0;
-    for (int b = b0; b < b1; ++b) {
-        const double mb = agg[2 * b];
-        const double eb = (mb == -INFINITY || M == -INFINITY) ? 0.0 : exp(mb - M);
-        agg[2 * b] = eb;
-        part += agg[2 * b + 1] * eb;
-    }
-    // 3. exclusive scan of the chunk sums: in the wave, then the waves in order
-    const double incl = wave_incl_sum(part);
-    if (lane == kWave - 1) s_red[wave] = incl;
-    __syncthreads();
-    double wbase = 0.0, S = 0.0;
-    for (int q = 0; q < NW; ++q) {
-        if (q == wave) wbase = S;
-        S += s_red[q];
-    }
-    double excl = wave_shr1(incl, 0.0);
-    excl += wbase;
-    const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
-    // 4. normalised affine constants, made non-decreasing (running max over
-    //    the chunk, then over the chunks' maxima)
-    double run = excl, amax = -INFINITY;
-    for (int b = b0; b < b1; ++b) {
-        const double eb = agg[2 * b];
-        amax = fmax(amax, ok ? run / S : 0.0);
-        ab[b] = TileAB{amax, ok ? eb / S : 0.0};
-        run += agg[2 * b + 1] * eb;
-    }
-    const double top = wave_incl_max(amax);
-    if (lane == kWave - 1) s_top[wave] = top;
-    __syncthreads();
-    double carry = -INFINITY;
-    for (int q = 0; q < wave; ++q) carry = fmax(carry, s_top[q]);
-    double ex = wave_shr1(top, -INFINITY);
-    carry = fmax(carry, ex);
-    if (carry > -INFINITY) {
-        for (int b = b0; b < b1; ++b) {
-            if (ab[b].a < carry) ab[b].a = carry;
-        }
-    }
-    __syncthreads();
-    // 5. search hints: tile b owns the output tiles h with
-    //    ceil(A_b n / ts) <= h < ceil(A_{b+1} n / ts); tile 0 starts at h = 0
-    //    and the last tile runs to h = tiles.  Every tile reads A_b and
-    //    A_{b+1} from the same stored table, so the ranges partition 0..tiles.
-    const double scale = static_cast<double>(n) / static_cast<double>(ts);
-    auto first_h = [&](int b) -> int64_t {
-        if (b == 0) return 0;
-        if (b >= T) return static_cast<int64_t>(T) + 1;
-        const double v = ceil(ab[b].a * scale);
-        return v > static_cast<double>(T) ? static_cast<int64_t>(T) : static_cast<int64_t>(v);
-    };
-    for (int b = b0; b < b1; ++b) {
-        const int64_t h0 = first_h(b), h1 = first_h(b + 1);
-        for (int64_t h = h0; h < h1; ++h) hint[h] = b;
-    }
-    if (tid == 0) {
-        tot->M = M;
-        tot->S = S;
-        if (!ok) atomicOr(&st->flags, kDegenerate);
-        st->loglik += M + log(S / static_cast<double>(n));
-    }
-}
-
-__global__ __launch_bounds__(kTileScanBlock) void k_scan_tiles(double* agg, int32_t num_tiles,
-                                                           int64_t n, int32_t ts, TileAB* ab,
-                                                           int32_t* hint, Totals* tot,
-                                                           DevState* st, const TileAB* pos) {
-    if (num_tiles <= kTileScanBlock * kTileScanPer)
-        scan_tiles_regs(agg, num_tiles, n, ts, ab, hint, tot, st, pos);
-    else
-        scan_tiles(agg, num_tiles, n, ts, ab, hint, tot, st);
+// Launched for at most kTileScanBlock * kTileScanPer tiles (more take the
+// chunked launches below).
+__global__ __launch_bounds__(kTileScanBlock) void k_scan_tiles(const double* agg,
+                                                           int32_t num_tiles, int64_t n,
+                                                           int32_t ts, TileAB* ab, int32_t* hint,
+                                                           Totals* tot, DevState* st,
+                                                           const TileAB* pos) {
+    scan_tiles_regs(agg, num_tiles, n, ts, ab, hint, tot, st, pos);
 }
 
 // ------------------------------------------------------------ chunked tile scan
@@ -1792,6 +1707,226 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const double* __restr
     for (int64_t h = h0; h < h1; ++h) hint[h] = static_cast<int32_t>(b);
 }
 
+// The chunked scan above, carried out by the one work-group of
+// kTileScanBlock threads that scans a batch member of more than
+// kTileScanBlock * kTileScanPer tiles: thread tid stands in for the threads
+// tid + r * kTileScanBlock (r < kVirt) of those kernels' work-groups of
+// kScanBlock threads.  Every wave-level reduction runs over the same 64
+// values in the same lanes and every sum over the waves adds them in the
+// same order, so the chunk aggregates, the prefixes P_c, M, S, the
+// log-likelihood increment, the table and the hints are the same bits as
+// the three launches' (a member gets the results it has when stepped
+// alone).  chunk: 3G + 1 doubles, as for those launches; agg is only read.
+constexpr int kVirt = kScanBlock / kTileScanBlock;
+static_assert(kVirt * kTileScanBlock == kScanBlock, "each thread stands in for whole lanes");
+
+struct VirtualBlock {
+    static constexpr int NW = kTileScanBlock / kWave;  // waves of this work-group
+    static constexpr int NV = kScanBlock / kWave;      // waves of the emulated one
+    double* s_red;                                      // NV doubles
+    int lane, wave;
+    __device__ int vwave(int r) const { return wave + NW * r; }
+    // block_max over the emulated work-group
+    __device__ double max(const double (&v)[kVirt]) const {
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            const double x = wave_max(v[r]);
+            if (lane == 0) s_red[vwave(r)] = x;
+        }
+        __syncthreads();
+        double m = -INFINITY;
+        for (int q = 0; q < NV; ++q) m = fmax(m, s_red[q]);
+        __syncthreads();
+        return m;
+    }
+    // block_excl_sum: out[r] = the exclusive prefix of virtual thread
+    // tid + r * kTileScanBlock; returns the total
+    __device__ double excl_sum(const double (&v)[kVirt], double (&out)[kVirt]) const {
+        double incl[kVirt];
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            incl[r] = wave_incl_sum(v[r]);
+            if (lane == kWave - 1) s_red[vwave(r)] = incl[r];
+        }
+        __syncthreads();
+        double base[kVirt], tot = 0.0;
+        for (int q = 0; q < NV; ++q) {
+#pragma unroll
+            for (int r = 0; r < kVirt; ++r)
+                if (q == vwave(r)) base[r] = tot;
+            tot += s_red[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            const double ex = wave_shr1(incl[r], 0.0);
+            out[r] = base[r] + ex;
+        }
+        return tot;
+    }
+    // block_excl_max (incl = false) or block_incl_max (incl = true)
+    __device__ void run_max(const double (&v)[kVirt], double (&out)[kVirt], bool inclusive) const {
+        double incl[kVirt];
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            incl[r] = wave_incl_max(v[r]);
+            if (lane == kWave - 1) s_red[vwave(r)] = incl[r];
+        }
+        __syncthreads();
+        double carry[kVirt];
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            carry[r] = -INFINITY;
+            for (int q = 0; q < vwave(r); ++q) carry[r] = fmax(carry[r], s_red[q]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r)
+            out[r] = inclusive ? fmax(incl[r], carry[r])
+                               : fmax(wave_shr1(incl[r], -INFINITY), carry[r]);
+    }
+};
+
+__device__ void scan_tiles_as_chunks(const double* __restrict__ agg, int32_t num_tiles, int64_t n,
+                                     int32_t ts, TileAB* __restrict__ ab,
+                                     int32_t* __restrict__ hint, Totals* tot, DevState* st,
+                                     double* chunk) {
+    __shared__ double s_red[VirtualBlock::NV];
+    __shared__ double s_a[kScanBlock];
+    const int tid = threadIdx.x;
+    const VirtualBlock B{s_red, lane_id(), tid / kWave};
+    const int T = num_tiles;
+    const int G = (T + kScanBlock - 1) / kScanBlock;
+    double* pref = chunk + 2 * static_cast<int64_t>(G);
+    auto load = [&](int c, double (&m)[kVirt], double (&sb)[kVirt]) {
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            const int64_t b = static_cast<int64_t>(c) * kScanBlock + tid + r * kTileScanBlock;
+            m[r] = -INFINITY;
+            sb[r] = 0.0;
+            if (b < T) {
+                const double2 v = reinterpret_cast<const double2*>(agg)[b];
+                m[r] = v.x;
+                sb[r] = v.y;
+            }
+        }
+    };
+    // k_scan_chunks, chunk by chunk (the next chunk's pairs loaded ahead)
+    double m[kVirt], sb[kVirt], mn[kVirt], sbn[kVirt];
+    load(0, m, sb);
+    for (int c = 0; c < G; ++c) {
+        if (c + 1 < G) load(c + 1, mn, sbn);
+        const double mc = B.max(m);
+        double w[kVirt], unused[kVirt];
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) w[r] = (m[r] == -INFINITY) ? 0.0 : sb[r] * exp(m[r] - mc);
+        const double sc = B.excl_sum(w, unused);
+        if (tid == 0) reinterpret_cast<double2*>(chunk)[c] = make_double2(mc, sc);
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            m[r] = mn[r];
+            sb[r] = sbn[r];
+        }
+    }
+    __syncthreads();
+    // k_scan_top
+    const int per = (G + kScanBlock - 1) / kScanBlock;
+    int g0[kVirt], g1[kVirt];
+    double mx[kVirt];
+#pragma unroll
+    for (int r = 0; r < kVirt; ++r) {
+        g0[r] = min(G, (tid + r * kTileScanBlock) * per);
+        g1[r] = min(G, g0[r] + per);
+        mx[r] = -INFINITY;
+        for (int g = g0[r]; g < g1[r]; ++g) mx[r] = fmax(mx[r], chunk[2 * g]);
+    }
+    const double M = B.max(mx);
+    auto weight = [&](int g) {
+        const double mg = chunk[2 * g];
+        return (mg == -INFINITY || M == -INFINITY) ? 0.0 : chunk[2 * g + 1] * exp(mg - M);
+    };
+    double part[kVirt], excl[kVirt], run[kVirt], carry[kVirt], fin[kVirt];
+#pragma unroll
+    for (int r = 0; r < kVirt; ++r) {
+        part[r] = 0.0;
+        for (int g = g0[r]; g < g1[r]; ++g) part[r] += weight(g);
+    }
+    B.excl_sum(part, excl);
+#pragma unroll
+    for (int r = 0; r < kVirt; ++r) {
+        run[r] = excl[r];
+        for (int g = g0[r]; g < g1[r]; ++g) run[r] += weight(g);
+    }
+    B.run_max(run, carry, false);
+#pragma unroll
+    for (int r = 0; r < kVirt; ++r) {
+        run[r] = excl[r];
+        for (int g = g0[r]; g < g1[r]; ++g) {
+            pref[g] = fmax(run[r], carry[r]);
+            run[r] += weight(g);
+        }
+        fin[r] = fmax(run[r], carry[r]);
+    }
+    const double S = B.max(fin);
+    const bool ok = (S > 0.0) && isfinite(S) && isfinite(M);
+    if (tid == 0) {
+        pref[G] = S;
+        tot->M = M;
+        tot->S = S;
+        if (st) {
+            if (!ok) atomicOr(&st->flags, kDegenerate);
+            st->loglik += M + log(S / static_cast<double>(n));
+        }
+    }
+    __syncthreads();
+    // k_scan_apply, chunk by chunk
+    const HintPos hp{nullptr, T, static_cast<double>(n) / static_cast<double>(ts)};
+    load(0, m, sb);
+    for (int c = 0; c < G; ++c) {
+        if (c + 1 < G) load(c + 1, mn, sbn);
+        const double lo = pref[c], hi = pref[c + 1];
+        double e[kVirt], pv[kVirt], ex[kVirt], a0[kVirt], a[kVirt];
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            e[r] = (m[r] == -INFINITY || M == -INFINITY) ? 0.0 : exp(m[r] - M);
+            pv[r] = sb[r] * e[r];
+        }
+        B.excl_sum(pv, ex);
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            const double x = lo + ex[r];
+            a0[r] = ok ? fmin(x, hi) / S : 0.0;
+        }
+        B.run_max(a0, a, true);
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            const int v = tid + r * kTileScanBlock;
+            const int64_t b = static_cast<int64_t>(c) * kScanBlock + v;
+            if (b < T) ab[b] = TileAB{a[r], ok ? e[r] / S : 0.0};
+            s_a[v] = a[r];
+        }
+        __syncthreads();
+        if (hint) {
+#pragma unroll
+            for (int r = 0; r < kVirt; ++r) {
+                const int v = tid + r * kTileScanBlock;
+                const int64_t b = static_cast<int64_t>(c) * kScanBlock + v;
+                if (b < T) {
+                    const double a_next = (v + 1 < kScanBlock) ? s_a[v + 1] : (ok ? hi / S : 0.0);
+                    const int64_t h0 = hp.first_h(b, a[r]), h1 = hp.first_h(b + 1, a_next);
+                    for (int64_t h = h0; h < h1; ++h) hint[h] = static_cast<int32_t>(b);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kVirt; ++r) {
+            m[r] = mn[r];
+            sb[r] = sbn[r];
+        }
+    }
+}
+
 // The batch's scans: work-group g scans filters g, g + grid, ... (those that
 // weighted this step); the last work-group to finish advances the batch's
 // step counter.
@@ -1806,8 +1941,14 @@ __global__ __launch_bounds__(kTileScanBlock) void k_scan_batch(const StepArgs* _
     __shared__ int s_count;
     for (int32_t f = blockIdx.x; f < n_filters; f += gridDim.x) {
         const StepArgs& A = d[f];
-        if ((A.flags & kWeight) && !(A.flags & kFusedScan))
-            scan_tiles(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out, A.tot_out, A.st);
+        if ((A.flags & kWeight) && !(A.flags & kFusedScan)) {
+            if (A.num_tiles <= kTileScanBlock * kTileScanPer)
+                scan_tiles_regs(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out, A.tot_out,
+                                A.st);
+            else
+                scan_tiles_as_chunks(A.agg_out, A.num_tiles, A.n, A.ts, A.ab_out, A.hint_out,
+                                     A.tot_out, A.st, A.chunk);
+        }
         __syncthreads();
         if ((A.flags & kWeight) && A.cut_in) {
             // the cut-point table of the CDF just weighed (the next step's

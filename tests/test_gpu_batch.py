@@ -162,23 +162,36 @@ def test_batch_errors(pf):
         f.close()
 
 
-def test_large_filter_alone_batched_alone(pf):
-    # a filter of more than 4096 tiles (its own tile scan runs in chunks, the
-    # batch's in one work-group per member) stepped alone, then in a batch,
-    # then alone again, equals the same filter stepped alone throughout
-    sizes = [4097 * 256 + 5, 3000]
+@pytest.mark.parametrize("n,ipt", [(4097 * 256 + 5, 1), (8193 * 1024 - 77, 4)])
+def test_large_filter_alone_batched_alone(pf, n, ipt):
+    # a filter of more than 4096 tiles (stepped alone its tile scan runs as
+    # three chunked launches; in a batch one work-group does the same
+    # arithmetic) stepped alone, then in a batch, then alone again, equals
+    # the same filter stepped alone throughout: results and the whole
+    # snapshot (CDF tables, chunk prefixes, totals) byte for byte
+    sizes = [n, 3000]
     T = 7
     y = _data("ll_pl", 2, T)
-    print(f"alone / batched / alone sizes={sizes}", flush=True)
-    ref = _make(pf, "ll_pl", sizes[:1], "stratified", True)[0]
-    f, g = _make(pf, "ll_pl", sizes, "stratified", True)
-    ref.step(y[:, 0])
+    print(f"alone / batched / alone sizes={sizes} ipt={ipt}", flush=True)
+    ref = _make(pf, "ll_pl", sizes[:1], "stratified", True, ipt=ipt)[0]
+    f, g = _make(pf, "ll_pl", sizes, "stratified", True, ipt=ipt)
+    snaps = []
+    ref.step(y[:5, 0])
+    snaps.append(ref.checkpoint())
+    ref.step(y[5:, 0])
+    snaps.append(ref.checkpoint())
     f.step(y[:3, 0])
     g.step(y[:3, 1])
     batch = pf.Batch([f, g])
     batch.step(y[3:5])
     batch.close()
+    got = [f.checkpoint()]
     f.step(y[5:, 0])
+    got.append(f.checkpoint())
+    for a, b in zip(snaps, got):
+        assert a.size == b.size
+        diff = np.flatnonzero(a != b)
+        assert diff.size == 0, f"snapshots differ at {diff.size} bytes from offset {diff[0]}"
     la, ra, aa, ta = _state(ref)
     lb, rb, ab_, tb = _state(f)
     assert ta == tb and la == lb
