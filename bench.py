@@ -64,17 +64,17 @@ TIMING_EVERY = 8
 # the bench reports null.
 COUNTER_SOURCES = ("pf_kernels.hip", "pf_models.hpp", "pf_internal.h")
 TRAFFIC = {
-    "ll_pl_2p20": dict(fetch_kib=14074.5, write_kib=24964.72, sources="46bb7911f8dcef05"),
-    "sv_pl_2p26": dict(fetch_kib=981147.61, write_kib=1990648.42, sources="46bb7911f8dcef05"),
+    "ll_pl_2p20": dict(fetch_kib=14073.86, write_kib=24964.15, sources="de01866dfaa5de0e"),
+    "sv_pl_2p26": dict(fetch_kib=981842.78, write_kib=1990648.57, sources="de01866dfaa5de0e"),
     # one batched step: k_step_batch + k_scan_batch
-    "ll_pl_batch256": dict(fetch_kib=239371.0, write_kib=442723.31, sources="46bb7911f8dcef05"),
+    "ll_pl_batch256": dict(fetch_kib=238748.0, write_kib=442723.26, sources="de01866dfaa5de0e"),
 }
 # Share of the SIMD cycles the cycle kernel's vector instructions occupy
 # (SQ_INSTS_VALU x 4 cycles per wave instruction over the kernel's clock
 # cycles x 1024 SIMDs), from a counter run of the same kernel sources.
 VALU_ISSUE = {
-    "ll_pl_2p20": dict(share=0.51, valu_per_particle=647, sources="46bb7911f8dcef05"),
-    "sv_pl_2p26": dict(share=0.94, valu_per_particle=570, sources="46bb7911f8dcef05"),
+    "ll_pl_2p20": dict(share=0.52, valu_per_particle=648, sources="de01866dfaa5de0e"),
+    "sv_pl_2p26": dict(share=0.95, valu_per_particle=566, sources="de01866dfaa5de0e"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
