@@ -202,7 +202,8 @@ int pf_loglik(const pf_filter* f, double* out);
  *     [E x_t, Var x_t, effective sample size].
  *   PF_LL_PL (equal weights, after propagation):
  *     [E x_t, Var x_t, mean of drawn sigma_v2, mean of drawn sigma_w2,
- *      Rao-Blackwell mean b_v/(a_v - 1), Rao-Blackwell mean b_w/(a_w - 1)].
+ *      Rao-Blackwell mean b_v/(a_v - 1), Rao-Blackwell mean b_w/(a_w - 1)]
+ *     (no effective sample size: with equal weights it is N).
  *   PF_SV_PL (weights of the latest step):
  *     [E x_t, Var x_t, E alpha, E beta, E sigma^2 of the draws,
  *      effective sample size, Rao-Blackwell mean of sigma^2].
