@@ -15,10 +15,10 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*``):
   LL-PL .................... pinned (known-theta limit = Kalman filter;
                              2-D quadrature x Kalman filter; path sums)
   SV-PF .................... pinned (1-D grid filter)
-  SV-PL .................... statistics pinned against least squares on the
-                             tracked path; the filter itself with unknown
-                             parameters is "parity unpinned" beyond
-                             N-consistency
+  SV-PL .................... pinned (statistics against least squares on
+                             the tracked path; known-parameter limit = 1-D
+                             grid filter; unknown parameters: quadrature
+                             over (alpha, beta, sigma^2) x grid filters)
 """
 from __future__ import annotations
 

@@ -7,8 +7,9 @@
   variances against the exact 2-D quadrature of Kalman filters.
 * The sufficient-statistic recursions, checked along the tracked ancestry.
 * SV-PF against a point-mass grid filter; SV-PL in the known-parameter limit
-  against the same grid filter; the SV posterior against least squares; the
-  parameter draw against its posterior law.
+  against the same grid filter, and with unknown parameters against
+  quadrature over (alpha, beta, sigma^2) of grid filters; the SV posterior
+  against least squares; the parameter draw against its posterior law.
 
 Monte Carlo comparisons average over seeds and use thresholds in standard
 errors estimated from the same seeds.
@@ -383,3 +384,24 @@ def test_sv_pl_single_block_draws_target_the_same_posterior(orc, y_sv):
         b = np.array([r["loglik"].sum() if col is None else r["moments"][-1, col] for r in two])
         se = np.sqrt(a.var(ddof=1) / a.size + b.var(ddof=1) / b.size)
         assert abs(a.mean() - b.mean()) < 4 * se, (col, a.mean(), b.mean(), se)
+
+
+def test_sv_pl_unknown_parameters_matches_quadrature(orc, y_sv):
+    # the whole unknown-parameter recursion (posterior of (alpha, beta,
+    # sigma^2) from each path's sums, the draw, the state move, the weights)
+    # against log p(y_{1:T}) and the posterior means by quadrature over the
+    # three parameters of exact grid filters; a prior with a cross term so
+    # that every entry of Lambda0 matters
+    y = y_sv[:50]
+    kw = dict(prior_mean=[-0.05, 0.95], prior_prec=[4.0, 2.0, 25.0], a_s=6.0, d_s=0.2,
+              x0_mean=-1.0, x0_var=0.4)
+    ex = cf.sv_pl_exact(y, **kw, n_box=13, reach=6.0, grid=161)
+    runs = _runs(orc, orc.SV_PL, 32768, range(12), y, orc.SYSTEMATIC, **kw)
+    tot = np.array([r["loglik"].sum() for r in runs])
+    se = tot.std(ddof=1) / np.sqrt(len(runs))
+    assert abs(tot.mean() - ex["loglik"]) < 4 * se + 0.03
+    last = np.array([r["moments"][-1] for r in runs])
+    # E alpha, E beta, E sigma^2 of the draws, Rao-Blackwell mean of sigma^2
+    for col, key in ((2, "e_alpha"), (3, "e_beta"), (4, "e_sigma2"), (6, "e_sigma2")):
+        se_c = last[:, col].std(ddof=1) / np.sqrt(len(runs))
+        assert abs(last[:, col].mean() - ex[key]) < 4 * se_c + 1e-3, (col, key)
